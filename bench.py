@@ -1,0 +1,292 @@
+#!/usr/bin/env python3
+"""Benchmark of the hologram hot path on one MI355X.
+
+One step = forward hologram (cgh_forward) of a 1,024-point cloud on a
+1,920 x 1,024 hologram (the paper's headline shape, Table 1 / abstract),
+G = I - T against a target hologram T, then the adjoint (cgh_backward) that
+yields dL/dx, dL/dy, dL/dz, dL/dA of L = 0.5 ||I - T||^2.  Inputs are seeded
+synthetic clouds already resident in HBM.
+
+Prints ONE JSON line: throughput in G point-pixel interactions per second
+(N * Nx * Ny / step time), the roofline record of the dominant kernel (the
+adjoint) from HIP events recorded around it, accuracy against the FP64 GPU
+forward, and the FP64 CPU oracle's rate on a bounded sample of the same
+workload (the cpu_baseline leg, the only part that touches the oracle).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Peak FP32 VALU issue rate of MI355X without packed math: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz lane-instructions per second.  Transcendentals (v_cos_f32,
+# v_sin_f32) issue at half rate on gfx950 (measured), i.e. 2 slots each.
+PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+TRANS_SLOTS = 2
+# Algorithmic VALU issue slots per point-pixel interaction of each kernel:
+#  fwd plain        dy, r2 (fma), Prev*r2, fract, cos, acc fma        = 5 + 2
+#  fwd compensated  X+Y add, cos, acc fma                             = 2 + 2
+#  adj plain        r2 (fma), Prev*r2, fract, sin, cos, Sc fma,
+#                   G*sin folded into column and row sums (2 fma)     = 6 + 4
+#  adj compensated  X+Y add, sin, cos, Sc fma, column/row sums (2)    = 4 + 4
+SLOTS = {
+    "fwd_plain": 5 + TRANS_SLOTS,
+    "fwd_compensated": 2 + TRANS_SLOTS,
+    "adj_plain": 6 + 2 * TRANS_SLOTS,
+    "adj_compensated": 4 + 2 * TRANS_SLOTS,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--variant", default="compensated", choices=["compensated", "plain"])
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="target wall seconds of each oracle sample (forward, adjoint)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def timed_steps(step, steps, torch):
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1002_0916_amd import binding as B
+    from paper_1002_0916_amd import workloads as W
+
+    B.load_library()
+    dev = torch.device("cuda:0")
+    wl = W.WORKLOADS["paper"]
+    nx, ny, n = wl.nx, wl.ny, wl.n
+    inter = wl.interactions
+    cloud = W.paper_cloud()
+    target = W.paper_target_cloud()
+    x, y, z, a = (torch.from_numpy(v).to(dev) for v in cloud.astuple())
+    tx, ty, tz, ta = (torch.from_numpy(v).to(dev) for v in target.astuple())
+    T = B.forward_f64(tx, ty, tz, ta, nx, ny).float()
+    I = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+    G = torch.empty_like(I)
+    torch.cuda.synchronize()
+
+    def make_step(variant):
+        def step():
+            B.forward(x, y, z, a, nx, ny, wl.pitch, wl.wavelength, variant, out=I)
+            torch.sub(I, T, out=G)
+            B.backward(x, y, z, a, G, nx, ny, wl.pitch, wl.wavelength, variant)
+        return step
+
+    results = {}
+    for variant in (args.variant, "plain" if args.variant == "compensated" else "compensated"):
+        step = make_step(variant)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        for k in range(5):
+            B.profile_read(k)  # clear
+        B.profile_enable(True)
+        ms, wall = timed_steps(step, args.steps, torch)
+        B.profile_enable(False)
+        fk = B.KERNEL_FWD_COMPENSATED if variant == "compensated" else B.KERNEL_FWD_PLAIN
+        ak = B.KERNEL_ADJ_COMPENSATED if variant == "compensated" else B.KERNEL_ADJ_PLAIN
+        nf, tf = B.profile_read(fk)
+        na, ta_ = B.profile_read(ak)
+        results[variant] = dict(ms_per_step=ms, wall_s=wall, fwd_kernel_ms=tf / max(nf, 1),
+                                adj_kernel_ms=ta_ / max(na, 1), fwd_launches=nf,
+                                adj_launches=na)
+
+    # Accuracy of the FP32 forward variants against the FP64 GPU forward.
+    I64 = B.forward_f64(x, y, z, a, nx, ny)
+    suma = float(np.sum(np.abs(cloud.a.astype(np.float64))))
+    errs = {}
+    for variant in ("plain", "compensated"):
+        Iv = B.forward(x, y, z, a, nx, ny, wl.pitch, wl.wavelength, variant)
+        errs[variant] = float((Iv.double() - I64).abs().max().item()) / suma
+    torch.cuda.synchronize()
+
+    main_r = results[args.variant]
+    ms = main_r["ms_per_step"]
+    value = inter / (ms * 1e-3) / 1e9
+    adj_key = "adj_" + args.variant
+    adj_ms = main_r["adj_kernel_ms"]
+    achieved = inter / (adj_ms * 1e-3) / 1e9
+    peak = PEAK_SLOTS / SLOTS[adj_key] / 1e9
+
+    def kernel_summary(variant):
+        r = results[variant]
+        return {
+            "ms_per_step": r["ms_per_step"],
+            "gpps": inter / (r["ms_per_step"] * 1e-3) / 1e9,
+            "fwd_kernel_ms": r["fwd_kernel_ms"],
+            "adj_kernel_ms": r["adj_kernel_ms"],
+            "fwd_gpps": inter / (r["fwd_kernel_ms"] * 1e-3) / 1e9,
+            "adj_gpps": inter / (r["adj_kernel_ms"] * 1e-3) / 1e9,
+            "fwd_roofline_frac": (inter / (r["fwd_kernel_ms"] * 1e-3)) /
+                                 (PEAK_SLOTS / SLOTS["fwd_" + variant]),
+            "adj_roofline_frac": (inter / (r["adj_kernel_ms"] * 1e-3)) /
+                                 (PEAK_SLOTS / SLOTS["adj_" + variant]),
+            "max_err_vs_fp64_over_sum_abs_a": errs[variant],
+        }
+
+    out = {
+        "metric": "Gpoint-pixel/s fwd+adjoint at 1920x1024, N=1024; % VALU peak; "
+                  "max err vs FP64",
+        "value": value,
+        "unit": "Gpoint-pixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded uniform point clouds)",
+        "config": {
+            "workload": "1920x1024 hologram, N=1024 points (x U[0,1920), y U[0,1024), "
+                        "z U[0.5,1.0] m, A U[0.5,1.0]), p=8e-6 m, lambda=633e-9 m",
+            "step": "forward + (I - T) + adjoint (dL/dx, dL/dy, dL/dz, dL/dA)",
+            "variant": args.variant,
+            "nx": nx, "ny": ny, "n_points": n,
+        },
+        "roofline": {
+            "kernel": adj_key,
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "Ginteraction/s",
+            "frac": achieved / peak,
+            "traffic": None,
+            "slots_per_interaction": SLOTS[adj_key],
+            "peak_slots_per_s": PEAK_SLOTS,
+            "kernel_ms": adj_ms,
+        },
+        "variants": {v: kernel_summary(v) for v in results},
+        "paper_context": {
+            "note": "forward only, Radeon HD5850, Table 1: 31 ms at N=1024",
+            "paper_forward_gpps": inter / 31e-3 / 1e9,
+            "this_forward_gpps": inter / (main_r["fwd_kernel_ms"] * 1e-3) / 1e9,
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cloud, target, nx, ny, wl, args.cpu_seconds, x, y,
+                                           z, a, T, args.variant, B, torch, np)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(cloud, target, nx, ny, wl, seconds, x, y, z, a, T, variant, B, torch, np):
+    """FP64 CPU oracle on a bounded sample of the same workload (all allowed cores).
+
+    Forward: the first R full rows (all N points); adjoint: P points over the full
+    grid, both sized from a short calibration to take about ``seconds`` each.
+    Combined rate = 1 / (1/r_fwd + 1/r_adj), the oracle's fwd+adjoint rate.
+    """
+    import oracle
+
+    cores = len(os.sched_getaffinity(0))
+    n = cloud.n
+    xs, ys, zs, as_ = cloud.astuple()
+
+    def fwd_rows(rows):
+        px = np.tile(np.arange(nx, dtype=np.int64), rows)
+        py = np.repeat(np.arange(rows, dtype=np.int64), nx)
+        t0 = time.perf_counter()
+        v = oracle.forward_at(xs, ys, zs, as_, nx, ny, px, py, wl.pitch, wl.wavelength,
+                              threads=cores)
+        return time.perf_counter() - t0, v
+
+    t_cal, _ = fwd_rows(max(1, cores // 4))
+    rate_f = max(1, cores // 4) * nx * n / t_cal
+    rows = int(min(ny, max(cores, seconds * rate_f / (nx * n))))
+    t_f, v_f = fwd_rows(rows)
+    r_f = rows * nx * n / t_f
+
+    # Adjoint sample with the same G as the GPU step (G = I - T).
+    I = B.forward(x, y, z, a, nx, ny, wl.pitch, wl.wavelength, variant)
+    Gd = (I - T)
+    G = Gd.cpu().numpy().astype(np.float64)
+    gg = B.backward(x, y, z, a, Gd.contiguous(), nx, ny, wl.pitch, wl.wavelength, variant)
+    gg = [t.cpu().numpy() for t in gg]
+    rng = np.random.default_rng(1234)
+    cal = np.arange(min(n, cores))
+    t0 = time.perf_counter()
+    oracle.adjoint(xs, ys, zs, as_, nx, ny, G, idx=cal, pitch=wl.pitch,
+                   wavelength=wl.wavelength, threads=cores)
+    rate_a = cal.shape[0] * nx * ny / (time.perf_counter() - t0)
+    npts = int(min(n, max(cores, seconds * rate_a / (nx * ny))))
+    npts = max(cores, (npts // cores) * cores) if npts >= cores else npts
+    idx = np.sort(rng.choice(n, size=min(npts, n), replace=False))
+    t0 = time.perf_counter()
+    ref = oracle.adjoint(xs, ys, zs, as_, nx, ny, G, idx=idx, pitch=wl.pitch,
+                         wavelength=wl.wavelength, threads=cores)
+    t_a = time.perf_counter() - t0
+    r_a = idx.shape[0] * nx * ny / t_a
+    combined = 1.0 / (1.0 / r_f + 1.0 / r_a)
+
+    Ig = I.cpu().numpy()[:rows].reshape(-1).astype(np.float64)
+    suma = float(np.sum(np.abs(as_.astype(np.float64))))
+    rel = {}
+    for name, g, r in zip("xyza", gg, ref):
+        rel["d" + name] = float(np.linalg.norm(g[idx] - r) / np.linalg.norm(r))
+    return {
+        "value": combined / 1e9,
+        "unit": "Gpoint-pixel/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": "forward: first %d of %d rows x all %d points (%.2f s); adjoint: %d of %d "
+                  "points x all %d pixels (%.2f s); FP64, libm cos/sin, %d threads"
+                  % (rows, ny, n, t_f, idx.shape[0], n, nx * ny, t_a, cores),
+        "fwd_gpps": r_f / 1e9,
+        "adj_gpps": r_a / 1e9,
+        "cpu_model": _cpu_model(),
+        "gpu_vs_oracle_on_sample": {
+            "variant": variant,
+            "fwd_max_err_over_sum_abs_a": float(np.max(np.abs(Ig - v_f)) / suma),
+            "grad_rel_l2": rel,
+        },
+    }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,317 @@
+// C ABI of the library (declared in include/cgh.h): argument checks,
+// workspace planning, kernel sequencing on the caller's stream, and optional
+// HIP-event timing of the main kernels.
+#include <math.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/cgh.h"
+#include "cgh_internal.h"
+
+namespace cgh {
+
+namespace {
+
+// 4,000,000 points pad to 62,500 waves of 64, within the 65,535 limit of the
+// adjoint grid's y dimension.
+constexpr int64_t kMaxPoints = 4000000;
+constexpr int32_t kMaxSide = 1 << 20;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
+
+Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
+  Plan p{};
+  p.n = n;
+  p.nx = nx;
+  p.ny = ny;
+  p.variant = variant;
+  p.op = op;
+  p.npad = ceil_div(n > 0 ? n : 1, kPointPad) * kPointPad;
+  p.fwd_gx = (int32_t)ceil_div(nx, kWave);
+  p.fwd_gy = (int32_t)ceil_div(ny, kFwdRowsPerWG);
+  p.groups = p.fwd_gy * kFwdWaves;
+  p.nbx = (int32_t)ceil_div(nx, kBlk);
+  p.nby = (int32_t)ceil_div(ny, kBlk);
+  p.ngroups = (int32_t)(p.npad / kWave);
+  const int64_t nblocks = (int64_t)p.nbx * p.nby;
+  int64_t regions = ceil_div(kAdjTargetWaves, p.ngroups);
+  if (regions > nblocks) regions = nblocks;
+  if (regions < 1) regions = 1;
+  p.blocks_per_region = (int32_t)ceil_div(nblocks, regions);
+  p.regions = (int32_t)ceil_div(nblocks, p.blocks_per_region);
+  p.need_gpad = (nx % kBlk) != 0 || (ny % kBlk) != 0;
+
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t np = (size_t)p.npad;
+  p.off_plain = take(np * sizeof(float4));
+  p.off_xrec = take(np * kAxisRec * sizeof(float));
+  p.off_yrec = take(np * kAxisRec * sizeof(float));
+  p.off_rec64 = op == CGH_OP_FORWARD_F64 ? take(np * sizeof(double4)) : 0;
+  p.off_ytab = (op == CGH_OP_FORWARD && variant == CGH_COMPENSATED)
+                   ? take((size_t)p.groups * np * kRows * sizeof(float))
+                   : 0;
+  p.off_partial = op == CGH_OP_BACKWARD ? take((size_t)p.regions * np * sizeof(float4)) : 0;
+  p.off_gpad = (op == CGH_OP_BACKWARD && p.need_gpad)
+                   ? take((size_t)p.nbx * kBlk * (size_t)p.nby * kBlk * sizeof(float))
+                   : 0;
+  p.total = off;
+  return p;
+}
+
+Workspace carve(const Plan& p, void* base) {
+  char* b = (char*)base;
+  Workspace w{};
+  w.plain = (float4*)(b + p.off_plain);
+  w.xrec = (float*)(b + p.off_xrec);
+  w.yrec = (float*)(b + p.off_yrec);
+  w.rec64 = p.op == CGH_OP_FORWARD_F64 ? (double4*)(b + p.off_rec64) : nullptr;
+  w.ytab = (p.op == CGH_OP_FORWARD && p.variant == CGH_COMPENSATED) ? (float*)(b + p.off_ytab)
+                                                                     : nullptr;
+  w.partial = p.op == CGH_OP_BACKWARD ? (float*)(b + p.off_partial) : nullptr;
+  w.gpad = (p.op == CGH_OP_BACKWARD && p.need_gpad) ? (float*)(b + p.off_gpad) : nullptr;
+  return w;
+}
+
+// ------------------------------------------------------------ profiling --
+
+namespace {
+
+struct EventPair {
+  hipEvent_t start, stop;
+};
+
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<EventPair> pool;                      // idle, reusable
+  std::vector<EventPair> pending[CGH_KERNEL_COUNT];  // recorded, unread
+};
+
+Profiler& profiler() {
+  static Profiler P;
+  return P;
+}
+
+constexpr size_t kMaxPending = 4096;
+
+// Records the start event of a timed launch; returns the pair to close, or a
+// pair of nulls when timing is off (or not possible).
+EventPair profile_begin(int kernel, hipStream_t s) {
+  Profiler& P = profiler();
+  std::lock_guard<std::mutex> lk(P.mu);
+  EventPair e{nullptr, nullptr};
+  if (!P.on || P.pending[kernel].size() >= kMaxPending) return e;
+  if (!P.pool.empty()) {
+    e = P.pool.back();
+    P.pool.pop_back();
+  } else {
+    if (hipEventCreate(&e.start) != hipSuccess) return EventPair{nullptr, nullptr};
+    if (hipEventCreate(&e.stop) != hipSuccess) {
+      (void)hipEventDestroy(e.start);
+      return EventPair{nullptr, nullptr};
+    }
+  }
+  if (hipEventRecord(e.start, s) != hipSuccess) {
+    P.pool.push_back(e);
+    return EventPair{nullptr, nullptr};
+  }
+  return e;
+}
+
+void profile_end(int kernel, EventPair e, hipStream_t s) {
+  if (!e.start) return;
+  Profiler& P = profiler();
+  std::lock_guard<std::mutex> lk(P.mu);
+  if (hipEventRecord(e.stop, s) != hipSuccess) {
+    P.pool.push_back(e);
+    return;
+  }
+  P.pending[kernel].push_back(e);
+}
+
+// ------------------------------------------------------------ validation --
+
+bool finite_positive(double v) { return isfinite(v) && v > 0.0; }
+
+int check_common(const float* x, const float* y, const float* z, const float* a, int64_t n,
+                 int32_t nx, int32_t ny, double pitch, double wavelength) {
+  if (n < 0 || n > kMaxPoints) return CGH_EINVAL;
+  if (nx < 1 || ny < 1 || nx > kMaxSide || ny > kMaxSide) return CGH_EINVAL;
+  if (n > 0 && (!x || !y || !z || !a)) return CGH_EINVAL;
+  if (!finite_positive(pitch) || !finite_positive(wavelength)) return CGH_EINVAL;
+  return CGH_OK;
+}
+
+int check_workspace(const Plan& p, void* ws, size_t bytes) {
+  if (p.total == 0) return CGH_OK;
+  if (!ws || bytes < p.total) return CGH_EWORKSPACE;
+  if (((uintptr_t)ws & 255u) != 0) return CGH_EWORKSPACE;
+  return CGH_OK;
+}
+
+inline int hip_status(hipError_t e) { return e == hipSuccess ? CGH_OK : CGH_EHIP; }
+
+}  // namespace
+
+}  // namespace cgh
+
+using namespace cgh;
+
+extern "C" {
+
+size_t cgh_workspace_bytes(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
+  if (op != CGH_OP_FORWARD && op != CGH_OP_FORWARD_F64 && op != CGH_OP_BACKWARD) return 0;
+  if (op != CGH_OP_FORWARD_F64 && variant != CGH_PLAIN && variant != CGH_COMPENSATED) return 0;
+  if (n < 0 || n > kMaxPoints || nx < 1 || ny < 1 || nx > kMaxSide || ny > kMaxSide) return 0;
+  if (n == 0) return 0;
+  return make_plan(n, nx, ny, variant, op).total;
+}
+
+int cgh_forward(const float* x, const float* y, const float* z, const float* a, int64_t n,
+                int32_t nx, int32_t ny, double pitch, double wavelength, int32_t variant,
+                float* hologram, void* workspace, size_t workspace_bytes, void* stream) {
+  int rc = check_common(x, y, z, a, n, nx, ny, pitch, wavelength);
+  if (rc) return rc;
+  if (variant != CGH_PLAIN && variant != CGH_COMPENSATED) return CGH_EINVAL;
+  if (!hologram) return CGH_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (n == 0) return hip_status(launch_fill_zero_f32(hologram, (int64_t)nx * ny, s));
+  const Plan p = make_plan(n, nx, ny, variant, CGH_OP_FORWARD);
+  rc = check_workspace(p, workspace, workspace_bytes);
+  if (rc) return rc;
+  const Workspace w = carve(p, workspace);
+  hipError_t e = launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, false, s);
+  if (e != hipSuccess) return CGH_EHIP;
+  if (variant == CGH_COMPENSATED) {
+    e = launch_ytab(p, w, s);
+    if (e != hipSuccess) return CGH_EHIP;
+    const EventPair ev = profile_begin(CGH_KERNEL_FWD_COMPENSATED, s);
+    e = launch_fwd_comp(p, w, hologram, s);
+    profile_end(CGH_KERNEL_FWD_COMPENSATED, ev, s);
+  } else {
+    const EventPair ev = profile_begin(CGH_KERNEL_FWD_PLAIN, s);
+    e = launch_fwd_plain(p, w, hologram, s);
+    profile_end(CGH_KERNEL_FWD_PLAIN, ev, s);
+  }
+  return hip_status(e);
+}
+
+int cgh_forward_f64(const float* x, const float* y, const float* z, const float* a, int64_t n,
+                    int32_t nx, int32_t ny, double pitch, double wavelength, double* hologram,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+  int rc = check_common(x, y, z, a, n, nx, ny, pitch, wavelength);
+  if (rc) return rc;
+  if (!hologram) return CGH_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (n == 0) return hip_status(launch_fill_zero_f64(hologram, (int64_t)nx * ny, s));
+  const Plan p = make_plan(n, nx, ny, CGH_PLAIN, CGH_OP_FORWARD_F64);
+  rc = check_workspace(p, workspace, workspace_bytes);
+  if (rc) return rc;
+  const Workspace w = carve(p, workspace);
+  hipError_t e = launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, true, s);
+  if (e != hipSuccess) return CGH_EHIP;
+  const EventPair ev = profile_begin(CGH_KERNEL_FWD_F64, s);
+  e = launch_fwd_f64(p, w, hologram, s);
+  profile_end(CGH_KERNEL_FWD_F64, ev, s);
+  return hip_status(e);
+}
+
+int cgh_backward(const float* x, const float* y, const float* z, const float* a, int64_t n,
+                 int32_t nx, int32_t ny, double pitch, double wavelength, int32_t variant,
+                 const float* grad_hologram, float* grad_x, float* grad_y, float* grad_z,
+                 float* grad_a, void* workspace, size_t workspace_bytes, void* stream) {
+  int rc = check_common(x, y, z, a, n, nx, ny, pitch, wavelength);
+  if (rc) return rc;
+  if (variant != CGH_PLAIN && variant != CGH_COMPENSATED) return CGH_EINVAL;
+  if (!grad_hologram) return CGH_EINVAL;
+  if (n > 0 && (!grad_x || !grad_y || !grad_z || !grad_a)) return CGH_EINVAL;
+  if (n == 0) return CGH_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const Plan p = make_plan(n, nx, ny, variant, CGH_OP_BACKWARD);
+  rc = check_workspace(p, workspace, workspace_bytes);
+  if (rc) return rc;
+  const Workspace w = carve(p, workspace);
+  hipError_t e = launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, false, s);
+  if (e != hipSuccess) return CGH_EHIP;
+  const float* g = grad_hologram;
+  int64_t ldg = nx;
+  if (p.need_gpad) {
+    e = launch_pad_g(p, grad_hologram, w.gpad, s);
+    if (e != hipSuccess) return CGH_EHIP;
+    g = w.gpad;
+    ldg = (int64_t)p.nbx * kBlk;
+  }
+  const int kid = variant == CGH_COMPENSATED ? CGH_KERNEL_ADJ_COMPENSATED : CGH_KERNEL_ADJ_PLAIN;
+  const EventPair ev = profile_begin(kid, s);
+  e = launch_adj_partial(p, w, g, ldg, s);
+  profile_end(kid, ev, s);
+  if (e != hipSuccess) return CGH_EHIP;
+  e = launch_adj_finalize(p, w, x, y, z, a, pitch, wavelength, grad_x, grad_y, grad_z, grad_a,
+                          s);
+  return hip_status(e);
+}
+
+const char* cgh_strerror(int status) {
+  switch (status) {
+    case CGH_OK:
+      return "success";
+    case CGH_EINVAL:
+      return "invalid argument";
+    case CGH_EWORKSPACE:
+      return "workspace missing, misaligned or too small";
+    case CGH_EHIP:
+      return "HIP launch or runtime error";
+    default:
+      return "unknown status";
+  }
+}
+
+int cgh_version(void) { return 100; }
+
+int cgh_profile_enable(int32_t on) {
+  Profiler& P = profiler();
+  std::lock_guard<std::mutex> lk(P.mu);
+  P.on = on != 0;
+  return CGH_OK;
+}
+
+int cgh_profile_read(int32_t kernel, int64_t* launches, double* total_ms) {
+  if (kernel < 0 || kernel >= CGH_KERNEL_COUNT || !launches || !total_ms) return CGH_EINVAL;
+  Profiler& P = profiler();
+  std::vector<EventPair> mine;
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    mine.swap(P.pending[kernel]);
+  }
+  int rc = CGH_OK;
+  double sum = 0.0;
+  int64_t count = 0;
+  for (const EventPair& e : mine) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(e.stop) != hipSuccess ||
+        hipEventElapsedTime(&ms, e.start, e.stop) != hipSuccess) {
+      rc = CGH_EHIP;
+      continue;
+    }
+    sum += ms;
+    ++count;
+  }
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    for (const EventPair& e : mine) P.pool.push_back(e);
+  }
+  *launches = count;
+  *total_ms = sum;
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal declarations shared by the library's HIP sources (not installed).
+//
+// Workspace layout, point-record formats and the launch wrappers of every
+// kernel.  All kernels target gfx950 (CDNA4, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cgh {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- forward --
+// A forward workgroup is 4 waves.  Lane l of every wave owns hologram column
+// x0 + l; wave w owns kRows consecutive rows, so a workgroup covers 64 columns
+// x (4 * kRows) rows and every lane produces kRows pixels of one column.
+constexpr int kFwdWaves = 4;
+constexpr int kRows = 8;
+constexpr int kFwdThreads = kFwdWaves * kWave;
+constexpr int kFwdRowsPerWG = kFwdWaves * kRows;
+// Points are processed in unrolled groups of kUnroll; the point arrays in the
+// workspace are padded to a multiple of kPointPad with zero-amplitude points.
+constexpr int kUnroll = 4;
+constexpr int kPointPad = 256;
+
+// ---------------------------------------------------------------- adjoint --
+// An adjoint wave holds 64 points (one per lane) and sweeps a region of
+// kBlk x kBlk pixel blocks; G is broadcast to the wave through scalar loads.
+constexpr int kBlk = 16;
+constexpr int kAdjThreads = kWave;
+// Aim for about this many waves per adjoint launch (256 CUs x 4 SIMDs x 8).
+constexpr int kAdjTargetWaves = 8192;
+
+// Point records, all produced on the device by the prep kernel from the FP32
+// inputs with FP64 arithmetic.
+//
+//  plain   float4 {x, y, Prev, A}         Prev = fl32(p^2 / (2 lambda z)),
+//                                           the phase coefficient in
+//                                           revolutions per pixel^2.
+//  axis    float[8] {c, Ph, Pl, b, d, A, v, 0} per axis (x then y arrays):
+//          c = rint(v) (v = x_j or y_j), f = v - c (exact),
+//          Ph = fl32(Prev), Pl = fl32(Prev - Ph),
+//          b = fl32(-2 Prev f), d = fl32(Prev f^2),
+//          so that Prev (h - v)^2 = (Ph + Pl) m^2 + b m + d with m = h - c,
+//          an integer: m^2 is exact in FP32 for |m| < 4096.
+//  f64     double4 {x, y, Prev, A}.
+constexpr int kAxisRec = 8;
+
+struct Workspace {
+  float4* plain;   // [npad]
+  float* xrec;     // [npad][8]
+  float* yrec;     // [npad][8]
+  double4* rec64;  // [npad]
+  float* ytab;     // forward, compensated: [groups][npad][kRows]
+  float* partial;  // adjoint: [regions][npad][4]
+  float* gpad;     // adjoint: G copied to a [nby*16][nbx*16] zero-padded grid
+};
+
+struct Plan {
+  int64_t n, npad;
+  int32_t nx, ny;
+  int32_t variant, op;
+  // forward
+  int32_t fwd_gx, fwd_gy, groups;
+  // adjoint
+  int32_t nbx, nby, blocks_per_region, regions, ngroups;
+  bool need_gpad;
+  size_t off_plain, off_xrec, off_yrec, off_rec64, off_ytab, off_partial, off_gpad, total;
+};
+
+Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op);
+Workspace carve(const Plan& p, void* base);
+
+// Launch wrappers (return the hipError_t of the launch).
+hipError_t launch_prep(const float* x, const float* y, const float* z, const float* a, int64_t n,
+                       int64_t npad, double pitch, double wavelength, const Workspace& w,
+                       bool want64, hipStream_t s);
+hipError_t launch_fill_zero_f32(float* p, int64_t count, hipStream_t s);
+hipError_t launch_fill_zero_f64(double* p, int64_t count, hipStream_t s);
+hipError_t launch_ytab(const Plan& p, const Workspace& w, hipStream_t s);
+hipError_t launch_fwd_plain(const Plan& p, const Workspace& w, float* out, hipStream_t s);
+hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s);
+hipError_t launch_fwd_f64(const Plan& p, const Workspace& w, double* out, hipStream_t s);
+hipError_t launch_pad_g(const Plan& p, const float* g, float* gpad, hipStream_t s);
+hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* g, int64_t ldg,
+                              hipStream_t s);
+hipError_t launch_adj_finalize(const Plan& p, const Workspace& w, const float* x, const float* y,
+                               const float* z, const float* a, double pitch, double wavelength,
+                               float* gx, float* gy, float* gz, float* ga, hipStream_t s);
+
+}  // namespace cgh

@@ -1,0 +1,194 @@
+"""Host-side checks of the C ABI (no GPU needed, no kernel launched).
+
+The library must load, export every function that include/cgh.h declares,
+size workspaces consistently, and reject bad arguments on the host before
+anything is enqueued.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cgh.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1002_0916_amd import binding
+
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_1002_0916_amd import build
+
+        build.build()
+    return binding.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cgh_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for required in ("cgh_forward", "cgh_forward_f64", "cgh_backward", "cgh_workspace_bytes",
+                     "cgh_strerror"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_header():
+    from paper_1002_0916_amd import binding
+
+    assert sorted(binding.EXPORTED) == declared_functions()
+
+
+def test_strerror_and_version(lib):
+    for code in range(4):
+        assert isinstance(lib.cgh_strerror(code), bytes) and lib.cgh_strerror(code)
+    assert lib.cgh_strerror(99) == b"unknown status"
+    assert lib.cgh_version() >= 100
+
+
+def test_workspace_bytes(lib):
+    from paper_1002_0916_amd import binding as B
+
+    f = lib.cgh_workspace_bytes
+    assert f(0, 16, 16, B.PLAIN, B.OP_FORWARD) == 0
+    assert f(-1, 16, 16, B.PLAIN, B.OP_FORWARD) == 0
+    assert f(10, 0, 16, B.PLAIN, B.OP_FORWARD) == 0
+    assert f(10, 16, 16, 7, B.OP_FORWARD) == 0
+    assert f(10, 16, 16, B.PLAIN, 9) == 0
+    assert f(4000001, 16, 16, B.PLAIN, B.OP_FORWARD) == 0
+    assert f(4000000, 16, 16, B.PLAIN, B.OP_BACKWARD) > 0
+    p = f(1024, 1920, 1024, B.PLAIN, B.OP_FORWARD)
+    c = f(1024, 1920, 1024, B.COMPENSATED, B.OP_FORWARD)
+    d = f(1024, 1920, 1024, B.PLAIN, B.OP_FORWARD_F64)
+    b = f(1024, 1920, 1024, B.COMPENSATED, B.OP_BACKWARD)
+    assert 0 < p < c and p < d and p < b
+    # the per-row phase table of the compensated forward: >= N * Ny floats
+    assert c - p >= 1024 * 1024 * 4
+    for v in (p, c, d, b):
+        assert v % 256 == 0
+    # monotone in N
+    assert f(4096, 1920, 1024, B.COMPENSATED, B.OP_BACKWARD) > b
+
+
+def _args(n=4):
+    dummy = ctypes.c_void_p(256)
+    return [dummy] * 4, n
+
+
+@pytest.mark.parametrize("case", ["null", "nx", "ny", "n", "pitch", "wl", "nan", "variant",
+                                  "out", "toolarge"])
+def test_forward_rejects_bad_arguments(lib, case):
+    from paper_1002_0916_amd import binding as B
+
+    p = ctypes.c_void_p(256)
+    args = dict(x=p, y=p, z=p, a=p, n=4, nx=8, ny=8, pitch=8e-6, wl=633e-9, v=B.PLAIN, out=p)
+    if case == "null":
+        args["y"] = None
+    elif case == "nx":
+        args["nx"] = 0
+    elif case == "ny":
+        args["ny"] = -3
+    elif case == "n":
+        args["n"] = -1
+    elif case == "pitch":
+        args["pitch"] = 0.0
+    elif case == "wl":
+        args["wl"] = -1.0
+    elif case == "nan":
+        args["pitch"] = float("nan")
+    elif case == "variant":
+        args["v"] = 5
+    elif case == "out":
+        args["out"] = None
+    elif case == "toolarge":
+        args["nx"] = (1 << 20) + 1
+    rc = lib.cgh_forward(args["x"], args["y"], args["z"], args["a"], args["n"], args["nx"],
+                         args["ny"], args["pitch"], args["wl"], args["v"], args["out"], p,
+                         1 << 30, None)
+    assert rc == B.CGH_EINVAL
+
+
+def test_workspace_too_small_or_misaligned(lib):
+    from paper_1002_0916_amd import binding as B
+
+    p = ctypes.c_void_p(256)
+    need = lib.cgh_workspace_bytes(100, 64, 64, B.COMPENSATED, B.OP_FORWARD)
+    rc = lib.cgh_forward(p, p, p, p, 100, 64, 64, 8e-6, 633e-9, B.COMPENSATED, p, p, need - 1,
+                         None)
+    assert rc == B.CGH_EWORKSPACE
+    rc = lib.cgh_forward(p, p, p, p, 100, 64, 64, 8e-6, 633e-9, B.COMPENSATED, p, None, need,
+                         None)
+    assert rc == B.CGH_EWORKSPACE
+    rc = lib.cgh_forward(p, p, p, p, 100, 64, 64, 8e-6, 633e-9, B.COMPENSATED, p,
+                         ctypes.c_void_p(256 + 4), need, None)
+    assert rc == B.CGH_EWORKSPACE
+    need_b = lib.cgh_workspace_bytes(100, 64, 64, B.PLAIN, B.OP_BACKWARD)
+    rc = lib.cgh_backward(p, p, p, p, 100, 64, 64, 8e-6, 633e-9, B.PLAIN, p, p, p, p, p, p,
+                          need_b - 256, None)
+    assert rc == B.CGH_EWORKSPACE
+    need_d = lib.cgh_workspace_bytes(100, 64, 64, B.PLAIN, B.OP_FORWARD_F64)
+    rc = lib.cgh_forward_f64(p, p, p, p, 100, 64, 64, 8e-6, 633e-9, p, p, need_d - 1, None)
+    assert rc == B.CGH_EWORKSPACE
+
+
+def test_backward_rejects_bad_arguments(lib):
+    from paper_1002_0916_amd import binding as B
+
+    p = ctypes.c_void_p(256)
+    ok = dict(gh=p, gx=p, gy=p, gz=p, ga=p)
+    for k in ok:
+        args = dict(ok)
+        args[k] = None
+        rc = lib.cgh_backward(p, p, p, p, 10, 32, 32, 8e-6, 633e-9, B.PLAIN, args["gh"],
+                              args["gx"], args["gy"], args["gz"], args["ga"], p, 1 << 30, None)
+        assert rc == B.CGH_EINVAL, k
+    rc = lib.cgh_backward(p, p, p, p, 10, 32, 32, 8e-6, 633e-9, 3, p, p, p, p, p, p, 1 << 30,
+                          None)
+    assert rc == B.CGH_EINVAL
+    # n = 0 is a valid no-op that enqueues nothing
+    rc = lib.cgh_backward(None, None, None, None, 0, 32, 32, 8e-6, 633e-9, B.PLAIN, p, None,
+                          None, None, None, None, 0, None)
+    assert rc == B.CGH_OK
+
+
+def test_profile_read_rejects_bad_kernel(lib):
+    from paper_1002_0916_amd import binding as B
+
+    n = ctypes.c_int64(0)
+    t = ctypes.c_double(0)
+    assert lib.cgh_profile_read(-1, ctypes.byref(n), ctypes.byref(t)) == B.CGH_EINVAL
+    assert lib.cgh_profile_read(5, ctypes.byref(n), ctypes.byref(t)) == B.CGH_EINVAL
+    assert lib.cgh_profile_read(0, None, ctypes.byref(t)) == B.CGH_EINVAL
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_1002_0916_amd import binding as B
+
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(B.CGHError):
+        B.load_library()
+
+
+def test_binding_validates_tensors():
+    import torch
+
+    from paper_1002_0916_amd import binding as B
+
+    if B._lib is None and not os.path.exists(B.LIB_PATH):
+        pytest.skip("library not built")
+    x = torch.zeros(4)
+    with pytest.raises(ValueError):
+        B.forward(x, x, x, x, 8, 8)  # CPU tensors are refused (no CPU path)
+    with pytest.raises(ValueError):
+        B.variant_id("fastest")
