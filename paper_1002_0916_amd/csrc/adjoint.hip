@@ -8,16 +8,19 @@
 // Work mapping: the transpose of the forward.  Lane = point, so each of the
 // four per-point reductions over pixels runs inside one lane and no
 // cross-lane reduction is needed at all.  A wave takes 64 points and a region
-// of 16 x 16 pixel blocks; G is wave-uniform and reaches the lanes through
-// scalar loads (one s_load_dwordx16 per block row).  Within a block the
-// pixel-dependent factors separate by axis: r^2 = dx^2 + dy^2, so the lane
-// accumulates the column sums and row sums of g_s = G sin(theta) and folds
-// them with dx_c, dx_c^2, dy_r, dy_r^2 once per block, leaving per
-// interaction: the phase, sin and cos, and four accumulations.
+// of the hologram: a strip of kAdjCols columns times a run of rows.  G is
+// wave-uniform and reaches the lanes through scalar loads, one strip row
+// (kAdjCols floats) at a time.  The pixel-dependent factors separate by axis,
+// r^2 = dx^2 + dy^2, so per strip the lane keeps the column phases (or dx) and
+// the column sums of G sin(theta) in registers, and per row it forms the row
+// phase (or dy^2) once and folds the row sum of G sin(theta) with dy and dy^2.
+// Per interaction that leaves the phase, sin and cos, and three fused
+// multiply-adds with G taken straight from an SGPR.
 //
-// Second pass: one thread per point adds the region partials in region
-// order (fixed, so the result is bitwise reproducible) in FP64 and applies
-// the per-point factors 2 A_j P_j and A_j P_j / z_j.
+// Second pass: kFinSlices threads per point add interleaved subsets of the
+// region partials in region order, then one thread adds the slice sums in
+// slice order (a fixed tree, so the result is bitwise reproducible), in FP64,
+// and applies the per-point factors 2 A_j P_j and A_j P_j / z_j.
 #include "cgh_internal.h"
 #include "phase.h"
 
@@ -28,109 +31,141 @@ namespace {
 template <int VARIANT>
 __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     const float4* __restrict__ plain, const float* __restrict__ xrec,
-    const float* __restrict__ yrec, const float* __restrict__ g, int64_t ldg, int nbx,
-    int nblocks, int bpr, int npad, float4* __restrict__ partial) {
+    const float* __restrict__ yrec, const float* __restrict__ g, int64_t ldg, int nsx,
+    int rows_per_seg, int ny, int npad, float4* __restrict__ partial) {
   const int region = blockIdx.x;
   const int j = blockIdx.y * kWave + threadIdx.x;
+  const int sx = region % nsx;
+  const int seg = region / nsx;
+  const int row0 = seg * rows_per_seg;
+  const int row1 = min(row0 + rows_per_seg, ny);
+  const int col0 = sx * kAdjCols;
 
-  // Per-lane point data.
-  float px, py, prev;
-  float xc = 0.f, xph = 0.f, xpl = 0.f, xb = 0.f, xd = 0.f;
+  const float4 pr = plain[j];
+  const float px = pr.x, py = pr.y, prev = pr.z;
   float yc = 0.f, yph = 0.f, ypl = 0.f, yb = 0.f, yd = 0.f;
-  {
-    const float4 r = plain[j];
-    px = r.x;
-    py = r.y;
-    prev = r.z;
-    if (VARIANT == 1) {
-      const float* rx = xrec + (int64_t)j * kAxisRec;
-      const float* ry = yrec + (int64_t)j * kAxisRec;
-      xc = rx[0]; xph = rx[1]; xpl = rx[2]; xb = rx[3]; xd = rx[4];
-      yc = ry[0]; yph = ry[1]; ypl = ry[2]; yb = ry[3]; yd = ry[4];
-    }
+  // Column terms: the compensated x-phase of each strip column, or dx.
+  float CX[kAdjCols];
+  if (VARIANT == 1) {
+    const float* rx = xrec + (int64_t)j * kAxisRec;
+    const float xc = rx[0], xph = rx[1], xpl = rx[2], xb = rx[3], xd = rx[4];
+    const float* ry = yrec + (int64_t)j * kAxisRec;
+    yc = ry[0]; yph = ry[1]; ypl = ry[2]; yb = ry[3]; yd = ry[4];
+#pragma unroll
+    for (int c = 0; c < kAdjCols; ++c)
+      CX[c] = axis_phase((float)(col0 + c), xc, xph, xpl, xb, xd);
+  } else {
+#pragma unroll
+    for (int c = 0; c < kAdjCols; ++c) CX[c] = (float)(col0 + c) - px;
   }
 
-  float Sc = 0.f, Sx = 0.f, Sy = 0.f, Sr = 0.f;
-  const int b0 = region * bpr;
-  const int b1 = min(b0 + bpr, nblocks);
-  for (int b = b0; b < b1; ++b) {
-    const int by = b / nbx;
-    const int bx = b - by * nbx;
-    const float x0 = (float)(bx * kBlk);
-    const float y0 = (float)(by * kBlk);
-    // Column terms (per lane): compensated x-phase, or dx for the plain form.
-    float CX[kBlk], RY[kBlk];
+  float SgC[kAdjCols];
 #pragma unroll
-    for (int c = 0; c < kBlk; ++c) {
-      const float h = x0 + (float)c;
-      CX[c] = VARIANT == 1 ? axis_phase(h, xc, xph, xpl, xb, xd) : h - px;
-    }
+  for (int c = 0; c < kAdjCols; ++c) SgC[c] = 0.f;
+  float Sc0 = 0.f, Sc1 = 0.f, Sy = 0.f, Sr = 0.f;
+  // G of one strip row lives in SGPRs.  Rows are software-pipelined with two
+  // ping-pong buffers: the scalar loads of the next row are issued right
+  // after the first use of the current row (which waits for it), so the rest
+  // of the row's arithmetic covers their latency.  The last row re-reads
+  // itself, so every load stays in bounds.
+  auto load_row = [&](int row, float* dst) {
+    const float* src = g + (int64_t)row * ldg + col0;
 #pragma unroll
-    for (int r = 0; r < kBlk; ++r) {
-      const float h = y0 + (float)r;
+    for (int k = 0; k < kAdjCols; ++k) dst[k] = src[k];
+  };
+  auto do_row = [&](int row, const float* gc, float* gn) {
+    const float yh = (float)row;
+    const float dy = yh - py;
+    const float dy2 = dy * dy;
+    const float RY = VARIANT == 1 ? axis_phase(yh, yc, yph, ypl, yb, yd) : dy2;
+    float sr0 = 0.f, sr1 = 0.f;
+#pragma unroll
+    for (int c = 0; c < kAdjCols; ++c) {
+      if (c == 1) {
+        __builtin_amdgcn_sched_barrier(0);
+        load_row(min(row + 1, row1 - 1), gn);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      const float G = gc[c];
+      float t;
       if (VARIANT == 1) {
-        RY[r] = axis_phase(h, yc, yph, ypl, yb, yd);
+        t = CX[c] + RY;
       } else {
-        const float dy = h - py;
-        RY[r] = dy * dy;
+        t = fract(prev * __builtin_fmaf(CX[c], CX[c], RY));
       }
-    }
-    float SgC[kBlk], SgR[kBlk];
-#pragma unroll
-    for (int c = 0; c < kBlk; ++c) SgC[c] = 0.f;
-    const float* __restrict__ gb = g + (int64_t)(by * kBlk) * ldg + bx * kBlk;
-#pragma unroll
-    for (int r = 0; r < kBlk; ++r) {
-      const float* __restrict__ gr = gb + (int64_t)r * ldg;
-      float sr = 0.f;
-#pragma unroll
-      for (int c = 0; c < kBlk; ++c) {
-        const float G = gr[c];
-        float t;
-        if (VARIANT == 1) {
-          t = CX[c] + RY[r];
-        } else {
-          t = fract(prev * __builtin_fmaf(CX[c], CX[c], RY[r]));
-        }
-        const float s = sin_rev(t);
-        const float co = cos_rev(t);
-        Sc = __builtin_fmaf(G, co, Sc);
-        const float gs = G * s;
-        SgC[c] += gs;
-        sr += gs;
+      const float s = sin_rev(t);
+      const float co = cos_rev(t);
+      if (c & 1) {
+        Sc1 = __builtin_fmaf(G, co, Sc1);
+        sr1 = __builtin_fmaf(G, s, sr1);
+      } else {
+        Sc0 = __builtin_fmaf(G, co, Sc0);
+        sr0 = __builtin_fmaf(G, s, sr0);
       }
-      SgR[r] = sr;
+      SgC[c] = __builtin_fmaf(G, s, SgC[c]);
     }
-#pragma unroll
-    for (int c = 0; c < kBlk; ++c) {
-      const float dx = (x0 + (float)c) - px;
-      Sx = __builtin_fmaf(dx, SgC[c], Sx);
-      Sr = __builtin_fmaf(dx * dx, SgC[c], Sr);
-    }
-#pragma unroll
-    for (int r = 0; r < kBlk; ++r) {
-      const float dy = (y0 + (float)r) - py;
-      Sy = __builtin_fmaf(dy, SgR[r], Sy);
-      Sr = __builtin_fmaf(dy * dy, SgR[r], Sr);
-    }
+    const float sr = sr0 + sr1;
+    Sy = __builtin_fmaf(dy, sr, Sy);
+    Sr = __builtin_fmaf(dy2, sr, Sr);
+  };
+  float gA[kAdjCols], gB[kAdjCols];
+  load_row(row0, gA);
+  int row = row0;
+  for (; row + 1 < row1; row += 2) {
+    do_row(row, gA, gB);
+    do_row(row + 1, gB, gA);
   }
-  partial[(int64_t)region * npad + j] = make_float4(Sc, Sx, Sy, Sr);
+  if (row < row1) do_row(row, gA, gB);
+  float Sx = 0.f;
+#pragma unroll
+  for (int c = 0; c < kAdjCols; ++c) {
+    const float dx = (float)(col0 + c) - px;
+    Sx = __builtin_fmaf(dx, SgC[c], Sx);
+    Sr = __builtin_fmaf(dx * dx, SgC[c], Sr);
+  }
+  partial[(int64_t)region * npad + j] = make_float4(Sc0 + Sc1, Sx, Sy, Sr);
 }
 
-__global__ __launch_bounds__(256) void adj_finalize_kernel(
+__global__ __launch_bounds__(kWave* kFinSlices) void adj_finalize_kernel(
     const float4* __restrict__ partial, int regions, int64_t npad, int64_t n,
-    const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
-    const float* __restrict__ a, double pitch, double wavelength, float* __restrict__ gx,
-    float* __restrict__ gy, float* __restrict__ gz, float* __restrict__ ga) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+    const float* __restrict__ z, const float* __restrict__ a, double pitch, double wavelength,
+    float* __restrict__ gx, float* __restrict__ gy, float* __restrict__ gz,
+    float* __restrict__ ga) {
+  __shared__ double part[kFinSlices][4][kWave];
+  const int lane = threadIdx.x;
+  const int slice = threadIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * kWave + lane;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (j < npad) {
+    // Regions slice, slice + kFinSlices, ... in increasing order.
+    int r = slice;
+    for (; r + 3 * kFinSlices < regions; r += 4 * kFinSlices) {
+      const float4 v0 = partial[(int64_t)r * npad + j];
+      const float4 v1 = partial[(int64_t)(r + kFinSlices) * npad + j];
+      const float4 v2 = partial[(int64_t)(r + 2 * kFinSlices) * npad + j];
+      const float4 v3 = partial[(int64_t)(r + 3 * kFinSlices) * npad + j];
+      s0 += (double)v0.x; s1 += (double)v0.y; s2 += (double)v0.z; s3 += (double)v0.w;
+      s0 += (double)v1.x; s1 += (double)v1.y; s2 += (double)v1.z; s3 += (double)v1.w;
+      s0 += (double)v2.x; s1 += (double)v2.y; s2 += (double)v2.z; s3 += (double)v2.w;
+      s0 += (double)v3.x; s1 += (double)v3.y; s2 += (double)v3.z; s3 += (double)v3.w;
+    }
+    for (; r < regions; r += kFinSlices) {
+      const float4 v = partial[(int64_t)r * npad + j];
+      s0 += (double)v.x; s1 += (double)v.y; s2 += (double)v.z; s3 += (double)v.w;
+    }
+  }
+  part[slice][0][lane] = s0;
+  part[slice][1][lane] = s1;
+  part[slice][2][lane] = s2;
+  part[slice][3][lane] = s3;
+  __syncthreads();
+  if (slice != 0 || j >= n) return;
   double Sc = 0.0, Sx = 0.0, Sy = 0.0, Sr = 0.0;
-  for (int r = 0; r < regions; ++r) {
-    const float4 v = partial[(int64_t)r * npad + j];
-    Sc += (double)v.x;
-    Sx += (double)v.y;
-    Sy += (double)v.z;
-    Sr += (double)v.w;
+  for (int k = 0; k < kFinSlices; ++k) {
+    Sc += part[k][0][lane];
+    Sx += part[k][1][lane];
+    Sy += part[k][2][lane];
+    Sr += part[k][3][lane];
   }
   const double zj = (double)z[j];
   const double aj = (double)a[j];
@@ -155,8 +190,8 @@ __global__ __launch_bounds__(256) void pad_g_kernel(const float* __restrict__ g,
 }  // namespace
 
 hipError_t launch_pad_g(const Plan& p, const float* g, float* gpad, hipStream_t s) {
-  const int ldp = p.nbx * kBlk;
-  const int64_t total = (int64_t)ldp * p.nby * kBlk;
+  const int ldp = p.nsx * kAdjCols;
+  const int64_t total = (int64_t)ldp * p.ny;
   hipLaunchKernelGGL(pad_g_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g,
                      p.nx, p.ny, ldp, total, gpad);
   return hipGetLastError();
@@ -165,15 +200,14 @@ hipError_t launch_pad_g(const Plan& p, const float* g, float* gpad, hipStream_t 
 hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* g, int64_t ldg,
                               hipStream_t s) {
   const dim3 grid(p.regions, p.ngroups);
-  const int nblocks = p.nbx * p.nby;
   if (p.variant == 1) {
     hipLaunchKernelGGL(adj_partial_kernel<1>, grid, dim3(kAdjThreads), 0, s,
                        (const float4*)w.plain, (const float*)w.xrec, (const float*)w.yrec, g, ldg,
-                       p.nbx, nblocks, p.blocks_per_region, (int)p.npad, (float4*)w.partial);
+                       p.nsx, p.rows_per_seg, p.ny, (int)p.npad, (float4*)w.partial);
   } else {
     hipLaunchKernelGGL(adj_partial_kernel<0>, grid, dim3(kAdjThreads), 0, s,
                        (const float4*)w.plain, (const float*)w.xrec, (const float*)w.yrec, g, ldg,
-                       p.nbx, nblocks, p.blocks_per_region, (int)p.npad, (float4*)w.partial);
+                       p.nsx, p.rows_per_seg, p.ny, (int)p.npad, (float4*)w.partial);
   }
   return hipGetLastError();
 }
@@ -181,9 +215,11 @@ hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* g,
 hipError_t launch_adj_finalize(const Plan& p, const Workspace& w, const float* x, const float* y,
                                const float* z, const float* a, double pitch, double wavelength,
                                float* gx, float* gy, float* gz, float* ga, hipStream_t s) {
-  hipLaunchKernelGGL(adj_finalize_kernel, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, s,
-                     (const float4*)w.partial, p.regions, p.npad, p.n, x, y, z, a, pitch,
-                     wavelength, gx, gy, gz, ga);
+  (void)x;
+  (void)y;
+  hipLaunchKernelGGL(adj_finalize_kernel, dim3((unsigned)((p.n + kWave - 1) / kWave)),
+                     dim3(kWave, kFinSlices), 0, s, (const float4*)w.partial, p.regions, p.npad,
+                     p.n, z, a, pitch, wavelength, gx, gy, gz, ga);
   return hipGetLastError();
 }
 

@@ -14,7 +14,7 @@ namespace cgh {
 namespace {
 
 // 4,000,000 points pad to 62,500 waves of 64, within the 65,535 limit of the
-// adjoint grid's y dimension.
+// adjoint grid's y dimension (the regions go in x).
 constexpr int64_t kMaxPoints = 4000000;
 constexpr int32_t kMaxSide = 1 << 20;
 
@@ -34,16 +34,16 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   p.fwd_gx = (int32_t)ceil_div(nx, kWave);
   p.fwd_gy = (int32_t)ceil_div(ny, kFwdRowsPerWG);
   p.groups = p.fwd_gy * kFwdWaves;
-  p.nbx = (int32_t)ceil_div(nx, kBlk);
-  p.nby = (int32_t)ceil_div(ny, kBlk);
   p.ngroups = (int32_t)(p.npad / kWave);
-  const int64_t nblocks = (int64_t)p.nbx * p.nby;
-  int64_t regions = ceil_div(kAdjTargetWaves, p.ngroups);
-  if (regions > nblocks) regions = nblocks;
-  if (regions < 1) regions = 1;
-  p.blocks_per_region = (int32_t)ceil_div(nblocks, regions);
-  p.regions = (int32_t)ceil_div(nblocks, p.blocks_per_region);
-  p.need_gpad = (nx % kBlk) != 0 || (ny % kBlk) != 0;
+  p.nsx = (int32_t)ceil_div(nx, kAdjCols);
+  int64_t nseg = ceil_div(kAdjTargetWaves, (int64_t)p.ngroups * p.nsx);
+  const int64_t max_seg = ceil_div(ny, kAdjMinRows);
+  if (nseg > max_seg) nseg = max_seg;
+  if (nseg < 1) nseg = 1;
+  p.rows_per_seg = (int32_t)ceil_div(ny, nseg);
+  p.nseg = (int32_t)ceil_div(ny, p.rows_per_seg);
+  p.regions = p.nsx * p.nseg;
+  p.need_gpad = (nx % kAdjCols) != 0;
 
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -53,6 +53,7 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   };
   const size_t np = (size_t)p.npad;
   p.off_plain = take(np * sizeof(float4));
+  p.off_amp = take(np * sizeof(float));
   p.off_xrec = take(np * kAxisRec * sizeof(float));
   p.off_yrec = take(np * kAxisRec * sizeof(float));
   p.off_rec64 = op == CGH_OP_FORWARD_F64 ? take(np * sizeof(double4)) : 0;
@@ -61,7 +62,7 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
                    : 0;
   p.off_partial = op == CGH_OP_BACKWARD ? take((size_t)p.regions * np * sizeof(float4)) : 0;
   p.off_gpad = (op == CGH_OP_BACKWARD && p.need_gpad)
-                   ? take((size_t)p.nbx * kBlk * (size_t)p.nby * kBlk * sizeof(float))
+                   ? take((size_t)p.nsx * kAdjCols * (size_t)ny * sizeof(float))
                    : 0;
   p.total = off;
   return p;
@@ -71,6 +72,7 @@ Workspace carve(const Plan& p, void* base) {
   char* b = (char*)base;
   Workspace w{};
   w.plain = (float4*)(b + p.off_plain);
+  w.amp = (float*)(b + p.off_amp);
   w.xrec = (float*)(b + p.off_xrec);
   w.yrec = (float*)(b + p.off_yrec);
   w.rec64 = p.op == CGH_OP_FORWARD_F64 ? (double4*)(b + p.off_rec64) : nullptr;
@@ -248,7 +250,7 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
     e = launch_pad_g(p, grad_hologram, w.gpad, s);
     if (e != hipSuccess) return CGH_EHIP;
     g = w.gpad;
-    ldg = (int64_t)p.nbx * kBlk;
+    ldg = (int64_t)p.nsx * kAdjCols;
   }
   const int kid = variant == CGH_COMPENSATED ? CGH_KERNEL_ADJ_COMPENSATED : CGH_KERNEL_ADJ_PLAIN;
   const EventPair ev = profile_begin(kid, s);

@@ -20,18 +20,32 @@ constexpr int kFwdWaves = 4;
 constexpr int kRows = 8;
 constexpr int kFwdThreads = kFwdWaves * kWave;
 constexpr int kFwdRowsPerWG = kFwdWaves * kRows;
-// Points are processed in unrolled groups of kUnroll; the point arrays in the
-// workspace are padded to a multiple of kPointPad with zero-amplitude points.
+// Points are processed in unrolled groups of kUnroll; the compensated
+// forward stages the x-phases of kTile points at a time in LDS (row stride
+// kTilePitch floats, padded so that lane-per-point writes hit distinct banks).  The point
+// arrays in the workspace are padded to a multiple of kPointPad with
+// zero-amplitude points.
 constexpr int kUnroll = 4;
-constexpr int kPointPad = 256;
+constexpr int kTile = 64;
+constexpr int kTilePitch = kWave + 1;
+// The compensated forward consumes kCompUnroll points per round trip of
+// scalar loads (kCompUnroll * kRows row phases + amplitudes in SGPRs, double
+// buffered).
+constexpr int kCompUnroll = 4;
+constexpr int kPointPad = 64;
 
 // ---------------------------------------------------------------- adjoint --
-// An adjoint wave holds 64 points (one per lane) and sweeps a region of
-// kBlk x kBlk pixel blocks; G is broadcast to the wave through scalar loads.
-constexpr int kBlk = 16;
+// An adjoint wave holds 64 points (one per lane) and sweeps a region: a strip
+// of kAdjCols hologram columns times a segment of consecutive rows.  G is
+// broadcast to the wave through scalar loads, one row of the strip at a time.
+constexpr int kAdjCols = 32;
 constexpr int kAdjThreads = kWave;
-// Aim for about this many waves per adjoint launch (256 CUs x 4 SIMDs x 8).
+// Aim for about this many waves per adjoint launch (256 CUs x 4 SIMDs x 8),
+// with at least kAdjMinRows rows per region.
 constexpr int kAdjTargetWaves = 8192;
+constexpr int kAdjMinRows = 8;
+// Second pass: kFinSlices threads per point add interleaved region subsets.
+constexpr int kFinSlices = 16;
 
 // Point records, all produced on the device by the prep kernel from the FP32
 // inputs with FP64 arithmetic.
@@ -50,12 +64,13 @@ constexpr int kAxisRec = 8;
 
 struct Workspace {
   float4* plain;   // [npad]
+  float* amp;      // [npad] amplitudes A_j (contiguous, for scalar loads)
   float* xrec;     // [npad][8]
   float* yrec;     // [npad][8]
   double4* rec64;  // [npad]
   float* ytab;     // forward, compensated: [groups][npad][kRows]
   float* partial;  // adjoint: [regions][npad][4]
-  float* gpad;     // adjoint: G copied to a [nby*16][nbx*16] zero-padded grid
+  float* gpad;     // adjoint: G copied to a [ny][nsx*kAdjCols] zero-padded grid
 };
 
 struct Plan {
@@ -64,10 +79,10 @@ struct Plan {
   int32_t variant, op;
   // forward
   int32_t fwd_gx, fwd_gy, groups;
-  // adjoint
-  int32_t nbx, nby, blocks_per_region, regions, ngroups;
+  // adjoint: regions = nsx column strips x nseg row segments
+  int32_t nsx, rows_per_seg, nseg, regions, ngroups;
   bool need_gpad;
-  size_t off_plain, off_xrec, off_yrec, off_rec64, off_ytab, off_partial, off_gpad, total;
+  size_t off_plain, off_amp, off_xrec, off_yrec, off_rec64, off_ytab, off_partial, off_gpad, total;
 };
 
 Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op);

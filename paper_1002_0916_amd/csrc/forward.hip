@@ -57,32 +57,97 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_plain_kernel(const float4* __
 // X_j(x_h) = Prev (x_h - x_j)^2 and Y_j(y_h) = Prev (y_h - y_j)^2.  Each part
 // is formed on the integer pixel grid as a compensated split product reduced
 // mod 1 (axis_phase).  Y comes from the per-row table (wave-uniform, scalar
-// loads); X is computed once per point per lane and reused for the lane's
-// kRows pixels.  Per interaction: one add, the native cosine (no fract: the
-// sum stays within a few revolutions) and one fma.
+// loads).  X depends on the column and the point only, and the four waves of
+// a workgroup share their 64 columns, so the workgroup computes X once per
+// tile of kTile points into LDS, double buffered so that filling tile t+1
+// overlaps consuming tile t.  For the fill, lane l holds point l of the tile
+// (its record arrives by one coalesced vector load, issued a tile ahead) and
+// wave w computes the 16 columns 16w..16w+15.  Per interaction: one LDS-fed
+// add, the native cosine (no fract: the sum stays within a few revolutions)
+// and one fma.
 __global__ __launch_bounds__(kFwdThreads) void fwd_comp_kernel(const float* __restrict__ xrec,
+                                                               const float* __restrict__ amp,
                                                                const float* __restrict__ ytab,
                                                                int npad, int nx, int ny,
                                                                float* __restrict__ out) {
+  __shared__ float xs[2][kTile * kTilePitch];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int col = blockIdx.x * kWave + lane;
+  const int col0 = blockIdx.x * kWave;
   const int grp = blockIdx.y * kFwdWaves + wave;
   const float xh = (float)col;
   const float* __restrict__ yt = ytab + (int64_t)grp * npad * kRows;
+  const int ntiles = npad / kTile;
+  constexpr int kColsPerWave = kWave / kFwdWaves;
+
+  // This lane's point record {c, Ph, Pl, b, d} for the tile being filled.
+  auto load_rec = [&](int tile, float4& r0, float& r1) {
+    const float* r = xrec + (int64_t)(tile * kTile + lane) * kAxisRec;
+    r0 = *reinterpret_cast<const float4*>(r);
+    r1 = r[4];
+  };
+  auto fill = [&](int buf, const float4& r0, float r1) {
+#pragma unroll
+    for (int k = 0; k < kColsPerWave; ++k) {
+      const int c = wave * kColsPerWave + k;
+      xs[buf][lane * kTilePitch + c] = axis_phase((float)(col0 + c), r0.x, r0.y, r0.z, r0.w, r1);
+    }
+  };
+  // Row phases and amplitudes of kCompUnroll consecutive points, read
+  // through scalar loads (SGPRs) and software-pipelined one group ahead: the
+  // loads of the next group are issued only after the first use of the
+  // current group (which waits for all outstanding scalar and LDS traffic),
+  // so the rest of the group's arithmetic covers their latency.
+  auto load_group = [&](int j, float* yv, float* av) {
+    const float* src = yt + (int64_t)j * kRows;
+#pragma unroll
+    for (int k = 0; k < kCompUnroll * kRows; ++k) yv[k] = src[k];
+#pragma unroll
+    for (int u = 0; u < kCompUnroll; ++u) av[u] = amp[j + u];
+  };
+
   float acc[kRows];
 #pragma unroll
   for (int i = 0; i < kRows; ++i) acc[i] = 0.0f;
-  for (int j = 0; j < npad; j += kUnroll) {
+  // Two ping-pong SGPR buffers; the last group re-reads itself (in bounds).
+  auto do_group = [&](const float* xt, int t, int p, const float* yv, const float* av,
+                      float* yn, float* an) {
+    float X[kCompUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const float* r = xrec + (int64_t)(j + u) * kAxisRec;
-      const float X = axis_phase(xh, r[0], r[1], r[2], r[3], r[4]);
-      const float A = r[5];
-      const float* yv = yt + (int64_t)(j + u) * kRows;
+    for (int u = 0; u < kCompUnroll; ++u) X[u] = xt[(p + u) * kTilePitch + lane];
 #pragma unroll
-      for (int i = 0; i < kRows; ++i) acc[i] = __builtin_fmaf(A, cos_rev(X + yv[i]), acc[i]);
+    for (int i = 0; i < kRows; ++i)
+      acc[i] = __builtin_fmaf(av[0], cos_rev(X[0] + yv[i]), acc[i]);
+    __builtin_amdgcn_sched_barrier(0);
+    load_group(min(t * kTile + p + kCompUnroll, npad - kCompUnroll), yn, an);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 1; u < kCompUnroll; ++u) {
+#pragma unroll
+      for (int i = 0; i < kRows; ++i)
+        acc[i] = __builtin_fmaf(av[u], cos_rev(X[u] + yv[u * kRows + i]), acc[i]);
     }
+  };
+  float yA[kCompUnroll * kRows], aA[kCompUnroll], yB[kCompUnroll * kRows], aB[kCompUnroll];
+  float4 r0;
+  float r1;
+  load_rec(0, r0, r1);
+  fill(0, r0, r1);
+  if (ntiles > 1) load_rec(1, r0, r1);
+  load_group(0, yA, aA);
+  __syncthreads();
+  for (int t = 0; t < ntiles; ++t) {
+    if (t + 1 < ntiles) {
+      fill((t + 1) & 1, r0, r1);
+      if (t + 2 < ntiles) load_rec(t + 2, r0, r1);
+    }
+    const float* xt = xs[t & 1];
+    for (int p = 0; p < kTile; p += 2 * kCompUnroll) {
+      do_group(xt, t, p, yA, aA, yB, aB);
+      do_group(xt, t, p + kCompUnroll, yB, aB, yA, aA);
+    }
+    __syncthreads();
   }
   const int y0 = grp * kRows;
   if (col < nx) {
@@ -123,7 +188,8 @@ hipError_t launch_fwd_plain(const Plan& p, const Workspace& w, float* out, hipSt
 
 hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s) {
   hipLaunchKernelGGL(fwd_comp_kernel, dim3(p.fwd_gx, p.fwd_gy), dim3(kFwdThreads), 0, s,
-                     (const float*)w.xrec, (const float*)w.ytab, (int)p.npad, p.nx, p.ny, out);
+                     (const float*)w.xrec, (const float*)w.amp, (const float*)w.ytab, (int)p.npad,
+                     p.nx, p.ny, out);
   return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ x,
                                                    const float* __restrict__ a, int64_t n,
                                                    int64_t npad, double pitch, double wavelength,
                                                    float4* __restrict__ plain,
+                                                   float* __restrict__ amp,
                                                    float* __restrict__ xrec,
                                                    float* __restrict__ yrec,
                                                    double4* __restrict__ rec64) {
@@ -35,6 +36,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ x,
   const float ph = (float)prev;
   const float pl = (float)(prev - (double)ph);
   plain[j] = make_float4(xs, ys, ph, as);
+  amp[j] = as;
 
   const float xc = rintf(xs), yc = rintf(ys);
   const double xf = (double)(xs - xc), yf = (double)(ys - yc);  // both exact
@@ -92,7 +94,7 @@ hipError_t launch_prep(const float* x, const float* y, const float* z, const flo
                        int64_t npad, double pitch, double wavelength, const Workspace& w,
                        bool want64, hipStream_t s) {
   hipLaunchKernelGGL(prep_kernel, dim3(blocks_for(npad, 256)), dim3(256), 0, s, x, y, z, a, n,
-                     npad, pitch, wavelength, w.plain, w.xrec, w.yrec,
+                     npad, pitch, wavelength, w.plain, w.amp, w.xrec, w.yrec,
                      want64 ? w.rec64 : (double4*)nullptr);
   return hipGetLastError();
 }
