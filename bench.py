@@ -53,7 +53,23 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=8.0,
                     help="target wall seconds of each oracle sample (forward, adjoint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="instead of the benchmark, run 5 plain device-to-device copies of this "
+                         "many bytes (a known-traffic reference for hardware byte counters)")
     return ap.parse_args()
+
+
+def copy_reference(nbytes):
+    """Plain device copies of a known size: the calibration kernel for the
+    FETCH_SIZE / WRITE_SIZE counters (each copy reads and writes nbytes)."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "copies": 5}), flush=True)
 
 
 def timed_steps(step, steps, torch):
@@ -77,6 +93,10 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_bytes > 0:
+        copy_reference(args.copy_bytes)
+        return
 
     import numpy as np
     import torch
