@@ -72,6 +72,27 @@ def copy_reference(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "copies": 5}), flush=True)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    record (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy reference), or
+    None when the kernel's sources have changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic_paper_1920x1024_n1024.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)["kernels"][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for name in rec["sources"]:
+        with open(os.path.join(ROOT, "paper_1002_0916_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["traffic_bytes"]
+
+
 def timed_steps(step, steps, torch):
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -205,7 +226,10 @@ def main():
             "peak": peak,
             "unit": "Ginteraction/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": measured_traffic("adj_partial_kernel<%d>"
+                                        % (1 if args.variant == "compensated" else 0)),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                            "copy-calibrated)",
             "slots_per_interaction": SLOTS[adj_key],
             "peak_slots_per_s": PEAK_SLOTS,
             "kernel_ms": adj_ms,

@@ -33,8 +33,10 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     const float4* __restrict__ plain, const float* __restrict__ xrec,
     const float* __restrict__ yrec, const float* __restrict__ g, int64_t ldg, int nsx,
     int rows_per_seg, int ny, int npad, float4* __restrict__ partial) {
-  const int region = blockIdx.x;
-  const int j = blockIdx.y * kWave + threadIdx.x;
+  // All point groups of a region read the same G strip: keep them on one XCD.
+  const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int region = (int)(tile / gridDim.y);
+  const int j = (int)(tile % gridDim.y) * kWave + threadIdx.x;
   const int sx = region % nsx;
   const int seg = region / nsx;
   const int row0 = seg * rows_per_seg;

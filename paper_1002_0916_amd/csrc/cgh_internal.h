@@ -11,6 +11,18 @@
 namespace cgh {
 
 constexpr int kWave = 64;
+constexpr int kXcds = 8;
+
+// MI355X dispatches workgroups round-robin over its 8 XCDs (linear id i runs
+// on XCD i % 8), each with its own L2.  xcd_tile renumbers linear id i of n
+// so that every XCD receives one contiguous range of tile indices: tiles
+// that are neighbours in tile order (and share input data) then share an L2.
+// A bijection on [0, n) for any n.
+__device__ __forceinline__ unsigned xcd_tile(unsigned i, unsigned n) {
+  const unsigned per = n / kXcds, rem = n % kXcds;
+  const unsigned x = i % kXcds, k = i / kXcds;
+  return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+}
 
 // ---------------------------------------------------------------- forward --
 // A forward workgroup is 4 waves.  Lane l of every wave owns hologram column

@@ -21,8 +21,10 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_plain_kernel(const float4* __
                                                                 float* __restrict__ out) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int col = blockIdx.x * kWave + lane;
-  const int y0 = (blockIdx.y * kFwdWaves + wave) * kRows;
+  const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int bx = (int)(tile % gridDim.x), by = (int)(tile / gridDim.x);
+  const int col = bx * kWave + lane;
+  const int y0 = (by * kFwdWaves + wave) * kRows;
   const float xh = (float)col;
   float yh[kRows];
   float acc[kRows];
@@ -73,9 +75,12 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_comp_kernel(const float* __re
   __shared__ float xs[2][kTile * kTilePitch];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int col = blockIdx.x * kWave + lane;
-  const int col0 = blockIdx.x * kWave;
-  const int grp = blockIdx.y * kFwdWaves + wave;
+  // Tiles of one tile row share their row-phase table: keep them on one XCD.
+  const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int bx = (int)(tile % gridDim.x), by = (int)(tile / gridDim.x);
+  const int col = bx * kWave + lane;
+  const int col0 = bx * kWave;
+  const int grp = by * kFwdWaves + wave;
   const float xh = (float)col;
   const float* __restrict__ yt = ytab + (int64_t)grp * npad * kRows;
   const int ntiles = npad / kTile;
