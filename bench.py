@@ -53,6 +53,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=8.0,
                     help="target wall seconds of each oracle sample (forward, adjoint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="paper",
+                    choices=["paper", "small", "mesh8k", "mesh64k", "adjoint", "fit4k"],
+                    help="paper: the headline fwd+adjoint step; the others print one report "
+                         "line for that workload instead")
+    ap.add_argument("--sweep", action="store_true",
+                    help="forward N-sweep at 1920x1024 (N = 512..3584, the Table 1 shapes)")
+    ap.add_argument("--fit-iters", type=int, default=100)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the benchmark, run 5 plain device-to-device copies of this "
                          "many bytes (a known-traffic reference for hardware byte counters)")
@@ -117,6 +124,12 @@ def main():
 
     if args.copy_bytes > 0:
         copy_reference(args.copy_bytes)
+        return
+    if args.sweep:
+        report_sweep(args)
+        return
+    if args.workload != "paper":
+        report_workload(args)
         return
 
     import numpy as np
@@ -319,6 +332,136 @@ def cpu_baseline(cloud, target, nx, ny, wl, seconds, x, y, z, a, T, variant, B, 
             "grad_rel_l2": rel,
         },
     }
+
+
+def _kernel_ms(B, torch, fn, kernel, reps):
+    """Average duration of ``kernel`` over ``reps`` calls of fn (library events)."""
+    fn()
+    torch.cuda.synchronize()
+    B.profile_read(kernel)
+    B.profile_enable(True)
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    B.profile_enable(False)
+    n, ms = B.profile_read(kernel)
+    return ms / max(n, 1)
+
+
+def _clouds(name, W):
+    if name == "small":
+        return W.small_cloud(), None
+    if name == "mesh8k":
+        return W.mesh_clouds()[0], None
+    if name == "mesh64k":
+        return W.mesh_clouds()[1], None
+    if name == "adjoint":
+        hidden, c = W.adjoint_clouds()
+        return c, hidden
+    if name == "fit4k":
+        hidden, c = W.fit_clouds()
+        return c, hidden
+    return W.paper_cloud(), W.paper_target_cloud()
+
+
+def report_workload(args):
+    """One JSON report line for a non-headline workload: forward kernel times
+    and errors against the FP64 GPU forward for both FP32 variants, the adjoint
+    kernel times, and for fit4k the Adam fitting loop."""
+    import numpy as np
+    import torch
+
+    from paper_1002_0916_amd import binding as B
+    from paper_1002_0916_amd import workloads as W
+
+    B.load_library()
+    dev = torch.device("cuda:0")
+    wl = W.WORKLOADS[args.workload]
+    nx, ny = wl.nx, wl.ny
+    cloud, hidden = _clouds(args.workload, W)
+    inter = cloud.n * nx * ny
+    x, y, z, a = (torch.from_numpy(v).to(dev) for v in cloud.astuple())
+    suma = float(np.sum(np.abs(cloud.a.astype(np.float64))))
+    reps = max(1, min(20, int(4e11 // inter)))
+    out = {"mode": "workload", "workload": args.workload, "description": wl.description,
+           "nx": nx, "ny": ny, "n_points": cloud.n, "interactions": inter, "reps": reps}
+
+    t64 = time.perf_counter()
+    I64 = B.forward_f64(x, y, z, a, nx, ny)
+    torch.cuda.synchronize()
+    out["fwd_f64_ms"] = (time.perf_counter() - t64) * 1e3
+    out["fwd_f64_gpps"] = inter / (out["fwd_f64_ms"] * 1e-3) / 1e9
+    for variant, fk, ak in (("plain", B.KERNEL_FWD_PLAIN, B.KERNEL_ADJ_PLAIN),
+                            ("compensated", B.KERNEL_FWD_COMPENSATED,
+                             B.KERNEL_ADJ_COMPENSATED)):
+        Iv = B.forward(x, y, z, a, nx, ny, wl.pitch, wl.wavelength, variant)
+        err = float((Iv.double() - I64).abs().max().item()) / suma
+        fms = _kernel_ms(B, torch, lambda: B.forward(x, y, z, a, nx, ny, wl.pitch,
+                                                     wl.wavelength, variant, out=Iv), fk, reps)
+        G = (Iv - I64.float()).contiguous() if hidden is None else None
+        if G is None:
+            hx, hy, hz, ha = (torch.from_numpy(v).to(dev) for v in hidden.astuple())
+            T = B.forward_f64(hx, hy, hz, ha, nx, ny).float()
+            G = (Iv - T).contiguous()
+        ams = _kernel_ms(B, torch, lambda: B.backward(x, y, z, a, G, nx, ny, wl.pitch,
+                                                      wl.wavelength, variant), ak, reps)
+        out[variant] = {
+            "fwd_kernel_ms": fms, "fwd_gpps": inter / (fms * 1e-3) / 1e9,
+            "fwd_roofline_frac": inter / (fms * 1e-3) / (PEAK_SLOTS / SLOTS["fwd_" + variant]),
+            "adj_kernel_ms": ams, "adj_gpps": inter / (ams * 1e-3) / 1e9,
+            "adj_roofline_frac": inter / (ams * 1e-3) / (PEAK_SLOTS / SLOTS["adj_" + variant]),
+            "max_err_vs_fp64_over_sum_abs_a": err,
+        }
+    if args.workload == "fit4k":
+        from paper_1002_0916_amd import fit as F
+
+        hx, hy, hz, ha = (torch.from_numpy(v).to(dev) for v in hidden.astuple())
+        T = B.forward_f64(hx, hy, hz, ha, nx, ny).float()
+        res = F.fit(x, y, z, a, T, nx, ny, iters=args.fit_iters, lr=1e-2, pitch=wl.pitch,
+                    wavelength=wl.wavelength, variant="compensated")
+        It = B.forward_f64(x, y, res.z, res.a, nx, ny)
+        Ic = B.forward(x, y, res.z, res.a, nx, ny, wl.pitch, wl.wavelength, "compensated")
+        suma_fit = float(res.a.abs().double().sum())
+        out["fit"] = {
+            "iterations": res.iterations, "seconds": res.seconds,
+            "iterations_per_s": res.iterations_per_s, "lr": 1e-2,
+            "params": "A and z/pitch (Adam); x, y fixed",
+            "loss_first": res.losses[0], "loss_last": res.losses[-1],
+            "loss_curve": res.losses,
+            "fwd_kernel_ms": res.fwd_ms, "adj_kernel_ms": res.adj_ms,
+            "fwd_gpps": inter / (res.fwd_ms * 1e-3) / 1e9,
+            "adj_gpps": inter / (res.adj_ms * 1e-3) / 1e9,
+            "fitted_fwd_max_err_vs_fp64_over_sum_abs_a":
+                float((Ic.double() - It).abs().max().item()) / suma_fit,
+        }
+    print(json.dumps(out), flush=True)
+
+
+def report_sweep(args):
+    """Forward kernel time against N at 1920x1024 (the Table 1 shapes and
+    beyond), both FP32 variants; the paper's HD5850 times are context."""
+    import torch
+
+    from paper_1002_0916_amd import binding as B
+    from paper_1002_0916_amd import workloads as W
+
+    B.load_library()
+    dev = torch.device("cuda:0")
+    paper_ms = {512: 19, 1024: 31, 1536: 44, 2048: 56, 2560: 68, 3072: 80, 3584: 93}
+    rows = []
+    for n in (512, 1024, 1536, 2048, 2560, 3072, 3584, 8192, 16384):
+        c = W.paper_cloud(n=n)
+        x, y, z, a = (torch.from_numpy(v).to(dev) for v in c.astuple())
+        I = torch.empty((1024, 1920), dtype=torch.float32, device=dev)
+        rec = {"n": n, "paper_hd5850_ms": paper_ms.get(n)}
+        for variant, k in (("plain", B.KERNEL_FWD_PLAIN),
+                           ("compensated", B.KERNEL_FWD_COMPENSATED)):
+            ms = _kernel_ms(B, torch, lambda: B.forward(x, y, z, a, 1920, 1024, variant=variant,
+                                                        out=I), k, 10)
+            rec[variant + "_ms"] = ms
+            rec[variant + "_gpps"] = n * 1920 * 1024 / (ms * 1e-3) / 1e9
+        rows.append(rec)
+    print(json.dumps({"mode": "sweep", "hologram": "1920x1024", "rows": rows}), flush=True)
 
 
 def _cpu_model():

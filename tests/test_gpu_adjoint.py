@@ -115,3 +115,40 @@ def test_autograd_function_matches_backward(variant):
     ref = B.backward(*(t.detach() for t in (x, y, z, a)), Wt, 120, 80, variant=variant)
     for t, r in zip((x, y, z, a), ref):
         assert torch.equal(t.grad, r)
+
+
+def test_adjoint_workload_against_central_differences(oracle_mod):
+    """The 1024x1024, 4096-point adjoint workload: G = I - T with T the FP64
+    hologram of the hidden cloud and I that of the perturbed cloud (oracle).
+    GPU gradients (compensated) of 32 seeded points are checked against central
+    differences of the FP64 loss 0.5 ||I - T||^2.  Steps: 1e-3 px in x, y,
+    1e-3 in A, 1e-3 of the 1 mm depth perturbation (1 um) in z.  Only point j's
+    term changes under a perturbation of point j, so each difference costs two
+    single-point holograms."""
+    dev = device()
+    nx = ny = 1024
+    hidden, c = W.adjoint_clouds()
+    say("oracle holograms of the hidden and perturbed clouds (4096 points, 1024^2)")
+    T = oracle_mod.forward(*hidden.astuple(), nx, ny, threads=0)
+    I = oracle_mod.forward(*c.astuple(), nx, ny, threads=0)
+    R = I - T
+    gg = gpu_grads(c, R.astype(np.float32), nx, ny, "compensated", dev)
+    idx = np.sort(np.random.default_rng(55).choice(c.n, size=32, replace=False))
+    x, y, z, a = (v.astype(np.float64) for v in c.astuple())
+    steps = {"x": 1e-3, "y": 1e-3, "z": 1e-6, "a": 1e-3}
+    for gi, name in enumerate(GROUPS):
+        fd = np.empty(idx.shape[0])
+        for t, j in enumerate(idx):
+            base = [x[j:j + 1], y[j:j + 1], z[j:j + 1], a[j:j + 1]]
+            old = oracle_mod.forward(*base, nx, ny)
+            k = "xyza".index(name)
+            vals = []
+            for sgn in (1.0, -1.0):
+                pert = [v.copy() for v in base]
+                pert[k] = pert[k] + sgn * steps[name]
+                new = oracle_mod.forward(*pert, nx, ny)
+                vals.append(0.5 * np.sum((R - old + new) ** 2))
+            fd[t] = (vals[0] - vals[1]) / (2 * steps[name])
+        e = rel_l2(gg[gi][idx], fd)
+        say("  d%s vs central differences rel-L2 = %.3e" % (name, e))
+        assert e <= TOL_ADJ["compensated"], (name, e)
