@@ -7,8 +7,9 @@
 //
 // Work mapping: the transpose of the forward.  Lane = point, so each of the
 // four per-point reductions over pixels runs inside one lane and no
-// cross-lane reduction is needed at all.  A wave takes 64 points and a region
-// of the hologram: a strip of kAdjCols columns times a run of rows.  G is
+// cross-lane reduction is needed at all.  A wave takes 64 points and an equal
+// share (a run) of the strip-rows of the hologram, where a strip is kAdjCols
+// columns wide; one round of resident waves covers everything.  G is
 // wave-uniform and reaches the lanes through scalar loads, one strip row
 // (kAdjCols floats) at a time.  The pixel-dependent factors separate by axis,
 // r^2 = dx^2 + dy^2, so per strip the lane keeps the column phases (or dx) and
@@ -21,6 +22,10 @@
 // region partials in region order, then one thread adds the slice sums in
 // slice order (a fixed tree, so the result is bitwise reproducible), in FP64,
 // and applies the per-point factors 2 A_j P_j and A_j P_j / z_j.
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "cgh_internal.h"
 #include "phase.h"
 
@@ -31,45 +36,37 @@ namespace {
 template <int VARIANT>
 __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     const float4* __restrict__ plain, const float* __restrict__ xrec,
-    const float* __restrict__ yrec, const float* __restrict__ g, int64_t ldg, int nsx,
-    int rows_per_seg, int ny, int npad, float4* __restrict__ partial) {
-  // All point groups of a region read the same G strip: keep them on one XCD.
+    const float* __restrict__ yrec, const float* __restrict__ g, int64_t ldg, int ny,
+    int64_t strip_rows, int npad, float4* __restrict__ partial) {
+  // Neighbouring runs and all point groups of a run share G: keep them on
+  // one XCD.
   const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  const int region = (int)(tile / gridDim.y);
+  const int run = (int)(tile / gridDim.y);
   const int j = (int)(tile % gridDim.y) * kWave + threadIdx.x;
-  const int sx = region % nsx;
-  const int seg = region / nsx;
-  const int row0 = seg * rows_per_seg;
-  const int row1 = min(row0 + rows_per_seg, ny);
-  const int col0 = sx * kAdjCols;
+  const int runs = (int)gridDim.x;
+  const int64_t q0 = strip_rows * run / runs;
+  const int64_t q1 = strip_rows * (run + 1) / runs;
 
   const float4 pr = plain[j];
   const float px = pr.x, py = pr.y, prev = pr.z;
+  float xc = 0.f, xph = 0.f, xpl = 0.f, xb = 0.f, xd = 0.f;
   float yc = 0.f, yph = 0.f, ypl = 0.f, yb = 0.f, yd = 0.f;
-  // Column terms: the compensated x-phase of each strip column, or dx.
-  float CX[kAdjCols];
   if (VARIANT == 1) {
     const float* rx = xrec + (int64_t)j * kAxisRec;
-    const float xc = rx[0], xph = rx[1], xpl = rx[2], xb = rx[3], xd = rx[4];
+    xc = rx[0]; xph = rx[1]; xpl = rx[2]; xb = rx[3]; xd = rx[4];
     const float* ry = yrec + (int64_t)j * kAxisRec;
     yc = ry[0]; yph = ry[1]; ypl = ry[2]; yb = ry[3]; yd = ry[4];
-#pragma unroll
-    for (int c = 0; c < kAdjCols; ++c)
-      CX[c] = axis_phase((float)(col0 + c), xc, xph, xpl, xb, xd);
-  } else {
-#pragma unroll
-    for (int c = 0; c < kAdjCols; ++c) CX[c] = (float)(col0 + c) - px;
   }
 
-  float SgC[kAdjCols];
-#pragma unroll
-  for (int c = 0; c < kAdjCols; ++c) SgC[c] = 0.f;
-  float Sc0 = 0.f, Sc1 = 0.f, Sy = 0.f, Sr = 0.f;
+  float Sc0 = 0.f, Sc1 = 0.f, Sx = 0.f, Sy = 0.f, Sr = 0.f;
+  float CX[kAdjCols], SgC[kAdjCols];
+  int col0 = 0, row1 = 0;
+
   // G of one strip row lives in SGPRs.  Rows are software-pipelined with two
   // ping-pong buffers: the scalar loads of the next row are issued right
   // after the first use of the current row (which waits for it), so the rest
-  // of the row's arithmetic covers their latency.  The last row re-reads
-  // itself, so every load stays in bounds.
+  // of the row's arithmetic covers their latency.  The last row of a segment
+  // re-reads itself, so every load stays in bounds.
   auto load_row = [&](int row, float* dst) {
     const float* src = g + (int64_t)row * ldg + col0;
 #pragma unroll
@@ -110,22 +107,37 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     Sy = __builtin_fmaf(dy, sr, Sy);
     Sr = __builtin_fmaf(dy2, sr, Sr);
   };
-  float gA[kAdjCols], gB[kAdjCols];
-  load_row(row0, gA);
-  int row = row0;
-  for (; row + 1 < row1; row += 2) {
-    do_row(row, gA, gB);
-    do_row(row + 1, gB, gA);
-  }
-  if (row < row1) do_row(row, gA, gB);
-  float Sx = 0.f;
+
+  // The run, one strip segment at a time (a run crosses at most a few strips).
+  for (int64_t q = q0; q < q1;) {
+    const int strip = (int)(q / ny);
+    const int row0 = (int)(q - (int64_t)strip * ny);
+    row1 = (int)min((int64_t)ny, row0 + (q1 - q));
+    col0 = strip * kAdjCols;
+    // Column terms: the compensated x-phase of each strip column, or dx.
 #pragma unroll
-  for (int c = 0; c < kAdjCols; ++c) {
-    const float dx = (float)(col0 + c) - px;
-    Sx = __builtin_fmaf(dx, SgC[c], Sx);
-    Sr = __builtin_fmaf(dx * dx, SgC[c], Sr);
+    for (int c = 0; c < kAdjCols; ++c) {
+      const float h = (float)(col0 + c);
+      CX[c] = VARIANT == 1 ? axis_phase(h, xc, xph, xpl, xb, xd) : h - px;
+      SgC[c] = 0.f;
+    }
+    float gA[kAdjCols], gB[kAdjCols];
+    load_row(row0, gA);
+    int row = row0;
+    for (; row + 1 < row1; row += 2) {
+      do_row(row, gA, gB);
+      do_row(row + 1, gB, gA);
+    }
+    if (row < row1) do_row(row, gA, gB);
+#pragma unroll
+    for (int c = 0; c < kAdjCols; ++c) {
+      const float dx = (float)(col0 + c) - px;
+      Sx = __builtin_fmaf(dx, SgC[c], Sx);
+      Sr = __builtin_fmaf(dx * dx, SgC[c], Sr);
+    }
+    q += row1 - row0;
   }
-  partial[(int64_t)region * npad + j] = make_float4(Sc0 + Sc1, Sx, Sy, Sr);
+  partial[(int64_t)run * npad + j] = make_float4(Sc0 + Sc1, Sx, Sy, Sr);
 }
 
 __global__ __launch_bounds__(kWave* kFinSlices) void adj_finalize_kernel(
@@ -199,29 +211,59 @@ hipError_t launch_pad_g(const Plan& p, const float* g, float* gpad, hipStream_t 
   return hipGetLastError();
 }
 
+int adj_runs(const Plan& p) {
+  // Resident single-wave workgroups per CU of each variant, per device.
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  int resident = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({dev, p.variant});
+    if (it != cache.end()) resident = it->second;
+  }
+  if (resident == 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return -1;
+    const hipError_t e =
+        p.variant == 1
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adj_partial_kernel<1>,
+                                                           kAdjThreads, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adj_partial_kernel<0>,
+                                                           kAdjThreads, 0);
+    if (e != hipSuccess || cus < 1 || per_cu < 1) return -1;
+    resident = cus * per_cu;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[{dev, p.variant}] = resident;
+  }
+  int runs = (resident + p.ngroups - 1) / p.ngroups;
+  if (runs > p.regions) runs = p.regions;
+  return runs < 1 ? 1 : runs;
+}
+
 hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* g, int64_t ldg,
-                              hipStream_t s) {
-  const dim3 grid(p.regions, p.ngroups);
+                              int runs, hipStream_t s) {
+  const dim3 grid(runs, p.ngroups);
   if (p.variant == 1) {
     hipLaunchKernelGGL(adj_partial_kernel<1>, grid, dim3(kAdjThreads), 0, s,
                        (const float4*)w.plain, (const float*)w.xrec, (const float*)w.yrec, g, ldg,
-                       p.nsx, p.rows_per_seg, p.ny, (int)p.npad, (float4*)w.partial);
+                       p.ny, p.strip_rows, (int)p.npad, (float4*)w.partial);
   } else {
     hipLaunchKernelGGL(adj_partial_kernel<0>, grid, dim3(kAdjThreads), 0, s,
                        (const float4*)w.plain, (const float*)w.xrec, (const float*)w.yrec, g, ldg,
-                       p.nsx, p.rows_per_seg, p.ny, (int)p.npad, (float4*)w.partial);
+                       p.ny, p.strip_rows, (int)p.npad, (float4*)w.partial);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_adj_finalize(const Plan& p, const Workspace& w, const float* x, const float* y,
-                               const float* z, const float* a, double pitch, double wavelength,
-                               float* gx, float* gy, float* gz, float* ga, hipStream_t s) {
-  (void)x;
-  (void)y;
+hipError_t launch_adj_finalize(const Plan& p, const Workspace& w, const float* z, const float* a,
+                               double pitch, double wavelength, int runs, float* gx, float* gy,
+                               float* gz, float* ga, hipStream_t s) {
   hipLaunchKernelGGL(adj_finalize_kernel, dim3((unsigned)((p.n + kWave - 1) / kWave)),
-                     dim3(kWave, kFinSlices), 0, s, (const float4*)w.partial, p.regions, p.npad,
-                     p.n, z, a, pitch, wavelength, gx, gy, gz, ga);
+                     dim3(kWave, kFinSlices), 0, s, (const float4*)w.partial, runs, p.npad, p.n,
+                     z, a, pitch, wavelength, gx, gy, gz, ga);
   return hipGetLastError();
 }
 

@@ -33,16 +33,16 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   p.npad = ceil_div(n > 0 ? n : 1, kPointPad) * kPointPad;
   p.fwd_gx = (int32_t)ceil_div(nx, kWave);
   p.fwd_gy = (int32_t)ceil_div(ny, kFwdRowsPerWG);
-  p.groups = p.fwd_gy * kFwdWaves;
+  p.comp_gy = (int32_t)ceil_div(ny, kCompRowsPerWG);
+  p.groups = p.comp_gy * kCompWaves;
   p.ngroups = (int32_t)(p.npad / kWave);
   p.nsx = (int32_t)ceil_div(nx, kAdjCols);
-  int64_t nseg = ceil_div(kAdjTargetWaves, (int64_t)p.ngroups * p.nsx);
-  const int64_t max_seg = ceil_div(ny, kAdjMinRows);
-  if (nseg > max_seg) nseg = max_seg;
-  if (nseg < 1) nseg = 1;
-  p.rows_per_seg = (int32_t)ceil_div(ny, nseg);
-  p.nseg = (int32_t)ceil_div(ny, p.rows_per_seg);
-  p.regions = p.nsx * p.nseg;
+  p.strip_rows = (int64_t)p.nsx * ny;
+  int64_t runs = ceil_div(kAdjMaxWaves, p.ngroups);
+  const int64_t max_runs = ceil_div(p.strip_rows, kAdjMinRun);
+  if (runs > max_runs) runs = max_runs;
+  if (runs < 1) runs = 1;
+  p.regions = (int32_t)runs;
   p.need_gpad = (nx % kAdjCols) != 0;
 
   size_t off = 0;
@@ -58,7 +58,7 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   p.off_yrec = take(np * kAxisRec * sizeof(float));
   p.off_rec64 = op == CGH_OP_FORWARD_F64 ? take(np * sizeof(double4)) : 0;
   p.off_ytab = (op == CGH_OP_FORWARD && variant == CGH_COMPENSATED)
-                   ? take((size_t)p.groups * np * kRows * sizeof(float))
+                   ? take((size_t)p.groups * np * kCompRows * sizeof(float))
                    : 0;
   p.off_partial = op == CGH_OP_BACKWARD ? take((size_t)p.regions * np * sizeof(float4)) : 0;
   p.off_gpad = (op == CGH_OP_BACKWARD && p.need_gpad)
@@ -252,13 +252,14 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
     g = w.gpad;
     ldg = (int64_t)p.nsx * kAdjCols;
   }
+  const int runs = adj_runs(p);
+  if (runs < 1) return CGH_EHIP;
   const int kid = variant == CGH_COMPENSATED ? CGH_KERNEL_ADJ_COMPENSATED : CGH_KERNEL_ADJ_PLAIN;
   const EventPair ev = profile_begin(kid, s);
-  e = launch_adj_partial(p, w, g, ldg, s);
+  e = launch_adj_partial(p, w, g, ldg, runs, s);
   profile_end(kid, ev, s);
   if (e != hipSuccess) return CGH_EHIP;
-  e = launch_adj_finalize(p, w, x, y, z, a, pitch, wavelength, grad_x, grad_y, grad_z, grad_a,
-                          s);
+  e = launch_adj_finalize(p, w, z, a, pitch, wavelength, runs, grad_x, grad_y, grad_z, grad_a, s);
   return hip_status(e);
 }
 

@@ -40,22 +40,45 @@ constexpr int kFwdRowsPerWG = kFwdWaves * kRows;
 constexpr int kUnroll = 4;
 constexpr int kTile = 64;
 constexpr int kTilePitch = kWave + 1;
-// The compensated forward consumes kCompUnroll points per round trip of
-// scalar loads (kCompUnroll * kRows row phases + amplitudes in SGPRs, double
-// buffered).
-constexpr int kCompUnroll = 4;
+
+// Compensated forward: a workgroup of kCompWaves waves covers 64 columns x
+// (kCompWaves * kCompRows) rows; each wave owns kCompRows rows and consumes
+// kCompUnroll points per round trip of scalar loads (kCompUnroll * kCompRows
+// row phases + amplitudes in SGPRs, double buffered).  Overridable at build
+// time for tuning experiments.
+#ifndef CGH_COMP_WAVES
+#define CGH_COMP_WAVES 8
+#endif
+#ifndef CGH_COMP_ROWS
+#define CGH_COMP_ROWS 4
+#endif
+#ifndef CGH_COMP_UNROLL
+#define CGH_COMP_UNROLL 8
+#endif
+constexpr int kCompWaves = CGH_COMP_WAVES;
+constexpr int kCompRows = CGH_COMP_ROWS;
+constexpr int kCompUnroll = CGH_COMP_UNROLL;
+constexpr int kCompThreads = kCompWaves * kWave;
+constexpr int kCompRowsPerWG = kCompWaves * kCompRows;
+static_assert(kWave % kCompWaves == 0, "x-phase fill splits the 64 columns over the waves");
+static_assert(kTile % (2 * kCompUnroll) == 0, "tiles hold whole ping-pong group pairs");
 constexpr int kPointPad = 64;
 
 // ---------------------------------------------------------------- adjoint --
-// An adjoint wave holds 64 points (one per lane) and sweeps a region: a strip
-// of kAdjCols hologram columns times a segment of consecutive rows.  G is
-// broadcast to the wave through scalar loads, one row of the strip at a time.
+// An adjoint wave holds 64 points (one per lane) and sweeps a run of
+// strip-rows: the hologram is cut into strips of kAdjCols columns, and the
+// strip-rows (strip-major: strip s, row r -> s * ny + r) of every point group
+// are split into equal contiguous runs, one per wave.  G is broadcast to the
+// wave through scalar loads, one strip row at a time.
 constexpr int kAdjCols = 32;
 constexpr int kAdjThreads = kWave;
-// Aim for about this many waves per adjoint launch (256 CUs x 4 SIMDs x 8),
-// with at least kAdjMinRows rows per region.
-constexpr int kAdjTargetWaves = 8192;
-constexpr int kAdjMinRows = 8;
+// At launch the number of runs is chosen so that one round of resident waves
+// (CUs x resident waves per CU, from the occupancy query) covers the whole
+// hologram with equal work per wave.  The partial-sum buffer is sized for at
+// most kAdjMaxWaves waves (256 CUs x 4 SIMDs x 8) and runs hold at least
+// kAdjMinRun strip-rows.
+constexpr int kAdjMaxWaves = 256 * 4 * 8;
+constexpr int kAdjMinRun = 8;
 // Second pass: kFinSlices threads per point add interleaved region subsets.
 constexpr int kFinSlices = 16;
 
@@ -80,7 +103,7 @@ struct Workspace {
   float* xrec;     // [npad][8]
   float* yrec;     // [npad][8]
   double4* rec64;  // [npad]
-  float* ytab;     // forward, compensated: [groups][npad][kRows]
+  float* ytab;     // forward, compensated: [groups][npad][kCompRows]
   float* partial;  // adjoint: [regions][npad][4]
   float* gpad;     // adjoint: G copied to a [ny][nsx*kAdjCols] zero-padded grid
 };
@@ -90,9 +113,11 @@ struct Plan {
   int32_t nx, ny;
   int32_t variant, op;
   // forward
-  int32_t fwd_gx, fwd_gy, groups;
-  // adjoint: regions = nsx column strips x nseg row segments
-  int32_t nsx, rows_per_seg, nseg, regions, ngroups;
+  int32_t fwd_gx, fwd_gy, comp_gy, groups;
+  // adjoint: runs of strip-rows per point group (regions = the most runs the
+  // partial buffer holds; the launch may use fewer)
+  int32_t nsx, regions, ngroups;
+  int64_t strip_rows;
   bool need_gpad;
   size_t off_plain, off_amp, off_xrec, off_yrec, off_rec64, off_ytab, off_partial, off_gpad, total;
 };
@@ -111,10 +136,13 @@ hipError_t launch_fwd_plain(const Plan& p, const Workspace& w, float* out, hipSt
 hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s);
 hipError_t launch_fwd_f64(const Plan& p, const Workspace& w, double* out, hipStream_t s);
 hipError_t launch_pad_g(const Plan& p, const float* g, float* gpad, hipStream_t s);
+// Runs per point group for this launch (<= p.regions), from the occupancy of
+// the adjoint kernel on the current device.
+int adj_runs(const Plan& p);
 hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* g, int64_t ldg,
-                              hipStream_t s);
-hipError_t launch_adj_finalize(const Plan& p, const Workspace& w, const float* x, const float* y,
-                               const float* z, const float* a, double pitch, double wavelength,
-                               float* gx, float* gy, float* gz, float* ga, hipStream_t s);
+                              int runs, hipStream_t s);
+hipError_t launch_adj_finalize(const Plan& p, const Workspace& w, const float* z, const float* a,
+                               double pitch, double wavelength, int runs, float* gx, float* gy,
+                               float* gz, float* ga, hipStream_t s);
 
 }  // namespace cgh

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_plain_kernel(const float4* __
 // wave w computes the 16 columns 16w..16w+15.  Per interaction: one LDS-fed
 // add, the native cosine (no fract: the sum stays within a few revolutions)
 // and one fma.
-__global__ __launch_bounds__(kFwdThreads) void fwd_comp_kernel(const float* __restrict__ xrec,
+__global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(const float* __restrict__ xrec,
                                                                const float* __restrict__ amp,
                                                                const float* __restrict__ ytab,
                                                                int npad, int nx, int ny,
@@ -80,11 +80,11 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_comp_kernel(const float* __re
   const int bx = (int)(tile % gridDim.x), by = (int)(tile / gridDim.x);
   const int col = bx * kWave + lane;
   const int col0 = bx * kWave;
-  const int grp = by * kFwdWaves + wave;
+  const int grp = by * kCompWaves + wave;
   const float xh = (float)col;
-  const float* __restrict__ yt = ytab + (int64_t)grp * npad * kRows;
+  const float* __restrict__ yt = ytab + (int64_t)grp * npad * kCompRows;
   const int ntiles = npad / kTile;
-  constexpr int kColsPerWave = kWave / kFwdWaves;
+  constexpr int kColsPerWave = kWave / kCompWaves;
 
   // This lane's point record {c, Ph, Pl, b, d} for the tile being filled.
   auto load_rec = [&](int tile, float4& r0, float& r1) {
@@ -105,16 +105,16 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_comp_kernel(const float* __re
   // current group (which waits for all outstanding scalar and LDS traffic),
   // so the rest of the group's arithmetic covers their latency.
   auto load_group = [&](int j, float* yv, float* av) {
-    const float* src = yt + (int64_t)j * kRows;
+    const float* src = yt + (int64_t)j * kCompRows;
 #pragma unroll
-    for (int k = 0; k < kCompUnroll * kRows; ++k) yv[k] = src[k];
+    for (int k = 0; k < kCompUnroll * kCompRows; ++k) yv[k] = src[k];
 #pragma unroll
     for (int u = 0; u < kCompUnroll; ++u) av[u] = amp[j + u];
   };
 
-  float acc[kRows];
+  float acc[kCompRows];
 #pragma unroll
-  for (int i = 0; i < kRows; ++i) acc[i] = 0.0f;
+  for (int i = 0; i < kCompRows; ++i) acc[i] = 0.0f;
   // Two ping-pong SGPR buffers; the last group re-reads itself (in bounds).
   auto do_group = [&](const float* xt, int t, int p, const float* yv, const float* av,
                       float* yn, float* an) {
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_comp_kernel(const float* __re
 #pragma unroll
     for (int u = 0; u < kCompUnroll; ++u) X[u] = xt[(p + u) * kTilePitch + lane];
 #pragma unroll
-    for (int i = 0; i < kRows; ++i)
+    for (int i = 0; i < kCompRows; ++i)
       acc[i] = __builtin_fmaf(av[0], cos_rev(X[0] + yv[i]), acc[i]);
     __builtin_amdgcn_sched_barrier(0);
     load_group(min(t * kTile + p + kCompUnroll, npad - kCompUnroll), yn, an);
@@ -130,11 +130,11 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_comp_kernel(const float* __re
 #pragma unroll
     for (int u = 1; u < kCompUnroll; ++u) {
 #pragma unroll
-      for (int i = 0; i < kRows; ++i)
-        acc[i] = __builtin_fmaf(av[u], cos_rev(X[u] + yv[u * kRows + i]), acc[i]);
+      for (int i = 0; i < kCompRows; ++i)
+        acc[i] = __builtin_fmaf(av[u], cos_rev(X[u] + yv[u * kCompRows + i]), acc[i]);
     }
   };
-  float yA[kCompUnroll * kRows], aA[kCompUnroll], yB[kCompUnroll * kRows], aB[kCompUnroll];
+  float yA[kCompUnroll * kCompRows], aA[kCompUnroll], yB[kCompUnroll * kCompRows], aB[kCompUnroll];
   float4 r0;
   float r1;
   load_rec(0, r0, r1);
@@ -154,10 +154,10 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_comp_kernel(const float* __re
     }
     __syncthreads();
   }
-  const int y0 = grp * kRows;
+  const int y0 = grp * kCompRows;
   if (col < nx) {
 #pragma unroll
-    for (int i = 0; i < kRows; ++i)
+    for (int i = 0; i < kCompRows; ++i)
       if (y0 + i < ny) out[(int64_t)(y0 + i) * nx + col] = acc[i];
   }
 }
@@ -192,7 +192,7 @@ hipError_t launch_fwd_plain(const Plan& p, const Workspace& w, float* out, hipSt
 }
 
 hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(fwd_comp_kernel, dim3(p.fwd_gx, p.fwd_gy), dim3(kFwdThreads), 0, s,
+  hipLaunchKernelGGL(fwd_comp_kernel, dim3(p.fwd_gx, p.comp_gy), dim3(kCompThreads), 0, s,
                      (const float*)w.xrec, (const float*)w.amp, (const float*)w.ytab, (int)p.npad,
                      p.nx, p.ny, out);
   return hipGetLastError();

@@ -61,16 +61,16 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ x,
   if (rec64) rec64[j] = make_double4((double)xs, (double)ys, prev, (double)as);
 }
 
-// ytab[g][j][i] = y-axis phase of point j at row g * kRows + i.
+// ytab[g][j][i] = y-axis phase of point j at row g * kCompRows + i.
 __global__ __launch_bounds__(256) void ytab_kernel(const float* __restrict__ yrec, int64_t npad,
                                                    int64_t total, float* __restrict__ ytab) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total) return;
-  const int64_t i = t % kRows;
-  const int64_t j = (t / kRows) % npad;
-  const int64_t g = t / (kRows * npad);
+  const int64_t i = t % kCompRows;
+  const int64_t j = (t / kCompRows) % npad;
+  const int64_t g = t / (kCompRows * npad);
   const float* r = yrec + j * kAxisRec;
-  const float h = (float)(g * kRows + i);
+  const float h = (float)(g * kCompRows + i);
   ytab[t] = axis_phase(h, r[0], r[1], r[2], r[3], r[4]);
 }
 
@@ -100,7 +100,7 @@ hipError_t launch_prep(const float* x, const float* y, const float* z, const flo
 }
 
 hipError_t launch_ytab(const Plan& p, const Workspace& w, hipStream_t s) {
-  const int64_t total = (int64_t)p.groups * p.npad * kRows;
+  const int64_t total = (int64_t)p.groups * p.npad * kCompRows;
   hipLaunchKernelGGL(ytab_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, w.yrec, p.npad,
                      total, w.ytab);
   return hipGetLastError();
