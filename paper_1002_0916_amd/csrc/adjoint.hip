@@ -238,7 +238,7 @@ int adj_runs(const Plan& p) {
     std::lock_guard<std::mutex> lk(mu);
     cache[{dev, p.variant}] = resident;
   }
-  int runs = (resident + p.ngroups - 1) / p.ngroups;
+  int runs = (kAdjRounds * resident + p.ngroups - 1) / p.ngroups;
   if (runs > p.regions) runs = p.regions;
   return runs < 1 ? 1 : runs;
 }

@@ -72,13 +72,17 @@ constexpr int kPointPad = 64;
 // wave through scalar loads, one strip row at a time.
 constexpr int kAdjCols = 32;
 constexpr int kAdjThreads = kWave;
-// At launch the number of runs is chosen so that one round of resident waves
-// (CUs x resident waves per CU, from the occupancy query) covers the whole
-// hologram with equal work per wave.  The partial-sum buffer is sized for at
+// At launch the number of runs is chosen so that kAdjRounds rounds of
+// resident waves (CUs x resident waves per CU, from the occupancy query)
+// cover the whole hologram with equal work per wave.  The partial-sum buffer is sized for at
 // most kAdjMaxWaves waves (256 CUs x 4 SIMDs x 8) and runs hold at least
 // kAdjMinRun strip-rows.
 constexpr int kAdjMaxWaves = 256 * 4 * 8;
 constexpr int kAdjMinRun = 8;
+#ifndef CGH_ADJ_ROUNDS
+#define CGH_ADJ_ROUNDS 3
+#endif
+constexpr int kAdjRounds = CGH_ADJ_ROUNDS;
 // Second pass: kFinSlices threads per point add interleaved region subsets.
 constexpr int kFinSlices = 16;
 
