@@ -42,6 +42,20 @@ SLOTS = {
     "adj_plain": 6 + 2 * TRANS_SLOTS,
     "adj_compensated": 4 + 2 * TRANS_SLOTS,
 }
+# The separable variant is a different algorithm, bound by the FP32 matrix
+# cores (dense MFMA FP32 peak 157.3 TFLOP/s): the forward is one GEMM of
+# 2 x (2N) flops per pixel (4 flops per interaction), the adjoint two
+# (8 flops per interaction).
+PEAK_MFMA_F32 = 157.3e12
+MFMA_FLOPS = {"fwd_separable": 4, "adj_separable": 8}
+
+
+def peak_interactions(key):
+    """Roofline peak (interactions/s) of a kernel: VALU issue for the direct
+    variants, FP32 matrix cores for the separable one."""
+    if key in MFMA_FLOPS:
+        return PEAK_MFMA_F32 / MFMA_FLOPS[key]
+    return PEAK_SLOTS / SLOTS[key]
 
 
 def parse():
@@ -49,7 +63,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--variant", default="compensated", choices=["compensated", "plain"])
+    ap.add_argument("--variant", default="compensated",
+                    choices=["compensated", "plain", "separable"])
     ap.add_argument("--cpu-seconds", type=float, default=8.0,
                     help="target wall seconds of each oracle sample (forward, adjoint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -98,6 +113,10 @@ def measured_traffic(kernel):
     if h.hexdigest()[:16] != rec["source_sha256_16"]:
         return None
     return rec["traffic_bytes"]
+
+
+FWD_KERNEL = {"plain": 0, "compensated": 1, "separable": 5}
+ADJ_KERNEL = {"plain": 3, "compensated": 4, "separable": 6}
 
 
 def timed_steps(step, steps, torch):
@@ -160,7 +179,8 @@ def main():
         return step
 
     results = {}
-    for variant in (args.variant, "plain" if args.variant == "compensated" else "compensated"):
+    others = [v for v in ("compensated", "plain", "separable") if v != args.variant]
+    for variant in [args.variant] + others:
         step = make_step(variant)
         for _ in range(args.warmup):
             step()
@@ -170,8 +190,8 @@ def main():
         B.profile_enable(True)
         ms, wall = timed_steps(step, args.steps, torch)
         B.profile_enable(False)
-        fk = B.KERNEL_FWD_COMPENSATED if variant == "compensated" else B.KERNEL_FWD_PLAIN
-        ak = B.KERNEL_ADJ_COMPENSATED if variant == "compensated" else B.KERNEL_ADJ_PLAIN
+        fk = FWD_KERNEL[variant]
+        ak = ADJ_KERNEL[variant]
         nf, tf = B.profile_read(fk)
         na, ta_ = B.profile_read(ak)
         results[variant] = dict(ms_per_step=ms, wall_s=wall, fwd_kernel_ms=tf / max(nf, 1),
@@ -182,7 +202,7 @@ def main():
     I64 = B.forward_f64(x, y, z, a, nx, ny)
     suma = float(np.sum(np.abs(cloud.a.astype(np.float64))))
     errs = {}
-    for variant in ("plain", "compensated"):
+    for variant in ("plain", "compensated", "separable"):
         Iv = B.forward(x, y, z, a, nx, ny, wl.pitch, wl.wavelength, variant)
         errs[variant] = float((Iv.double() - I64).abs().max().item()) / suma
     torch.cuda.synchronize()
@@ -193,7 +213,7 @@ def main():
     adj_key = "adj_" + args.variant
     adj_ms = main_r["adj_kernel_ms"]
     achieved = inter / (adj_ms * 1e-3) / 1e9
-    peak = PEAK_SLOTS / SLOTS[adj_key] / 1e9
+    peak = peak_interactions(adj_key) / 1e9
 
     def kernel_summary(variant):
         r = results[variant]
@@ -205,9 +225,9 @@ def main():
             "fwd_gpps": inter / (r["fwd_kernel_ms"] * 1e-3) / 1e9,
             "adj_gpps": inter / (r["adj_kernel_ms"] * 1e-3) / 1e9,
             "fwd_roofline_frac": (inter / (r["fwd_kernel_ms"] * 1e-3)) /
-                                 (PEAK_SLOTS / SLOTS["fwd_" + variant]),
+                                 peak_interactions("fwd_" + variant),
             "adj_roofline_frac": (inter / (r["adj_kernel_ms"] * 1e-3)) /
-                                 (PEAK_SLOTS / SLOTS["adj_" + variant]),
+                                 peak_interactions("adj_" + variant),
             "max_err_vs_fp64_over_sum_abs_a": errs[variant],
         }
 
@@ -234,7 +254,7 @@ def main():
         },
         "roofline": {
             "kernel": adj_key,
-            "bound": "alu",
+            "bound": "mfma" if args.variant == "separable" else "alu",
             "achieved": achieved,
             "peak": peak,
             "unit": "Ginteraction/s",
@@ -243,7 +263,8 @@ def main():
                                         % (1 if args.variant == "compensated" else 0)),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                             "copy-calibrated)",
-            "slots_per_interaction": SLOTS[adj_key],
+            "slots_per_interaction": SLOTS.get(adj_key),
+            "flops_per_interaction": MFMA_FLOPS.get(adj_key),
             "peak_slots_per_s": PEAK_SLOTS,
             "kernel_ms": adj_ms,
         },
@@ -393,7 +414,8 @@ def report_workload(args):
     out["fwd_f64_gpps"] = inter / (out["fwd_f64_ms"] * 1e-3) / 1e9
     for variant, fk, ak in (("plain", B.KERNEL_FWD_PLAIN, B.KERNEL_ADJ_PLAIN),
                             ("compensated", B.KERNEL_FWD_COMPENSATED,
-                             B.KERNEL_ADJ_COMPENSATED)):
+                             B.KERNEL_ADJ_COMPENSATED),
+                            ("separable", B.KERNEL_FWD_SEPARABLE, B.KERNEL_ADJ_SEPARABLE)):
         Iv = B.forward(x, y, z, a, nx, ny, wl.pitch, wl.wavelength, variant)
         err = float((Iv.double() - I64).abs().max().item()) / suma
         fms = _kernel_ms(B, torch, lambda: B.forward(x, y, z, a, nx, ny, wl.pitch,
@@ -407,9 +429,9 @@ def report_workload(args):
                                                       wl.wavelength, variant), ak, reps)
         out[variant] = {
             "fwd_kernel_ms": fms, "fwd_gpps": inter / (fms * 1e-3) / 1e9,
-            "fwd_roofline_frac": inter / (fms * 1e-3) / (PEAK_SLOTS / SLOTS["fwd_" + variant]),
+            "fwd_roofline_frac": inter / (fms * 1e-3) / peak_interactions("fwd_" + variant),
             "adj_kernel_ms": ams, "adj_gpps": inter / (ams * 1e-3) / 1e9,
-            "adj_roofline_frac": inter / (ams * 1e-3) / (PEAK_SLOTS / SLOTS["adj_" + variant]),
+            "adj_roofline_frac": inter / (ams * 1e-3) / peak_interactions("adj_" + variant),
             "max_err_vs_fp64_over_sum_abs_a": err,
         }
     if args.workload == "fit4k":

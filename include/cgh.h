@@ -45,6 +45,13 @@
  *                       mod 1 revolution; exact-grid arithmetic holds while
  *                       |x_h - rint(x_j)| and |y_h - rint(y_j)| stay below
  *                       4096 pixels.
+ *      CGH_SEPARABLE    not the per-interaction cosine: the phase separates
+ *                       exactly into x and y parts (each formed as in
+ *                       CGH_COMPENSATED), cos(X + Y) = cXcY - sXsY turns the sum
+ *                       into a dense real contraction of per-axis tables, and
+ *                       the forward and adjoint run as FP32 matrix-core GEMMs.
+ *                       Needs a larger workspace (tables of 2N floats per row
+ *                       and per column, plus split-K partial planes).
  *    FP64 appears only in the per-point precompute of P_j / (2 pi) and its
  *    hi/lo split (and in cgh_forward_f64).
  */
@@ -67,6 +74,7 @@ extern "C" {
 /* Phase-arithmetic variants. */
 #define CGH_PLAIN 0
 #define CGH_COMPENSATED 1
+#define CGH_SEPARABLE 2
 
 /* Operations, for cgh_workspace_bytes. */
 #define CGH_OP_FORWARD 0
@@ -79,7 +87,9 @@ extern "C" {
 #define CGH_KERNEL_FWD_F64 2
 #define CGH_KERNEL_ADJ_PLAIN 3
 #define CGH_KERNEL_ADJ_COMPENSATED 4
-#define CGH_KERNEL_COUNT 5
+#define CGH_KERNEL_FWD_SEPARABLE 5 /* the forward GEMM */
+#define CGH_KERNEL_ADJ_SEPARABLE 6 /* both adjoint GEMMs, one event pair */
+#define CGH_KERNEL_COUNT 7
 
 /*
  * Bytes of device workspace that `op` (CGH_OP_*) needs for n points on an
@@ -96,7 +106,7 @@ size_t cgh_workspace_bytes(int64_t n, int32_t nx, int32_t ny, int32_t variant, i
  *                and amplitudes A_j.
  *   hologram     device float32[ny][nx], overwritten with I.  n = 0 writes
  *                zeros.
- *   variant      CGH_PLAIN or CGH_COMPENSATED.
+ *   variant      CGH_PLAIN, CGH_COMPENSATED or CGH_SEPARABLE.
  */
 int cgh_forward(const float* x, const float* y, const float* z, const float* a, int64_t n,
                 int32_t nx, int32_t ny, double pitch, double wavelength, int32_t variant,

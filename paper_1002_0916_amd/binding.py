@@ -27,12 +27,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcgh.so")
 
 CGH_OK, CGH_EINVAL, CGH_EWORKSPACE, CGH_EHIP = 0, 1, 2, 3
-PLAIN, COMPENSATED = 0, 1
+PLAIN, COMPENSATED, SEPARABLE = 0, 1, 2
 OP_FORWARD, OP_FORWARD_F64, OP_BACKWARD = 0, 1, 2
 KERNEL_FWD_PLAIN, KERNEL_FWD_COMPENSATED, KERNEL_FWD_F64 = 0, 1, 2
 KERNEL_ADJ_PLAIN, KERNEL_ADJ_COMPENSATED = 3, 4
+KERNEL_FWD_SEPARABLE, KERNEL_ADJ_SEPARABLE = 5, 6
 
-VARIANTS = {"plain": PLAIN, "fast": PLAIN, "compensated": COMPENSATED, "comp": COMPENSATED}
+VARIANTS = {"plain": PLAIN, "fast": PLAIN, "compensated": COMPENSATED, "comp": COMPENSATED,
+            "separable": SEPARABLE}
 
 EXPORTED = ("cgh_workspace_bytes", "cgh_forward", "cgh_forward_f64", "cgh_backward",
             "cgh_strerror", "cgh_version", "cgh_profile_enable", "cgh_profile_read")
@@ -88,13 +90,13 @@ def _check(rc: int):
 
 def variant_id(variant) -> int:
     if isinstance(variant, int):
-        if variant not in (PLAIN, COMPENSATED):
+        if variant not in (PLAIN, COMPENSATED, SEPARABLE):
             raise ValueError("unknown variant %r" % variant)
         return variant
     try:
         return VARIANTS[variant]
     except KeyError:
-        raise ValueError("unknown variant %r (plain|compensated)" % (variant,)) from None
+        raise ValueError("unknown variant %r (plain|compensated|separable)" % (variant,)) from None
 
 
 def workspace_bytes(n: int, nx: int, ny: int, variant=COMPENSATED, op: int = OP_FORWARD) -> int:

@@ -21,6 +21,16 @@ constexpr int32_t kMaxSide = 1 << 20;
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Split-K count for a GEMM of `tiles` 128 x 128 output tiles and contraction
+// length k (a multiple of 128): double it while the grid stays within about
+// 1024 workgroups (two rounds of two per CU), each slice keeps >= 256 of k,
+// and slices stay multiples of 32.
+inline int gemm_splits(int64_t tiles, int64_t k) {
+  int s = 1;
+  while (tiles * s * 2 <= 1024 && (k / 32) % (s * 2) == 0 && k / (s * 2) >= 256) s *= 2;
+  return s;
+}
+
 }  // namespace
 
 Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
@@ -45,6 +55,14 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   p.regions = (int32_t)runs;
   p.need_gpad = (nx % kAdjCols) != 0;
 
+  // Separable variant: padded GEMM shapes and split-K counts.
+  p.nxp = (int32_t)ceil_div(nx, 128) * 128;
+  p.nyp = (int32_t)ceil_div(ny, 128) * 128;
+  p.k2 = 2 * p.npad;
+  p.sep_splits = gemm_splits((int64_t)(p.nyp / 128) * (p.nxp / 128), p.k2);
+  p.sep_splits_u = gemm_splits((p.k2 / 128) * (p.nxp / 128), p.nyp);
+  p.sep_splits_p = gemm_splits((p.k2 / 128) * (p.nyp / 128), p.nxp);
+
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -60,10 +78,27 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   p.off_ytab = (op == CGH_OP_FORWARD && variant == CGH_COMPENSATED)
                    ? take((size_t)p.groups * np * kCompRows * sizeof(float))
                    : 0;
-  p.off_partial = op == CGH_OP_BACKWARD ? take((size_t)p.regions * np * sizeof(float4)) : 0;
-  p.off_gpad = (op == CGH_OP_BACKWARD && p.need_gpad)
+  const bool direct_adj = op == CGH_OP_BACKWARD && variant != CGH_SEPARABLE;
+  p.off_partial = direct_adj ? take((size_t)p.regions * np * sizeof(float4)) : 0;
+  p.off_gpad = (direct_adj && p.need_gpad)
                    ? take((size_t)p.nsx * kAdjCols * (size_t)ny * sizeof(float))
                    : 0;
+  const bool sep = variant == CGH_SEPARABLE && op != CGH_OP_FORWARD_F64;
+  const size_t k2 = (size_t)p.k2;
+  p.off_sep_x = sep ? take((size_t)p.nxp * k2 * sizeof(float)) : 0;
+  p.off_sep_y = sep ? take((size_t)p.nyp * k2 * sizeof(float)) : 0;
+  p.off_sep_c = (sep && op == CGH_OP_FORWARD && p.sep_splits > 1)
+                    ? take((size_t)p.sep_splits * p.nyp * (size_t)p.nxp * sizeof(float))
+                    : 0;
+  p.off_sep_g = (sep && op == CGH_OP_BACKWARD)
+                    ? take((size_t)p.nyp * (size_t)p.nxp * sizeof(float))
+                    : 0;
+  p.off_sep_u = (sep && op == CGH_OP_BACKWARD)
+                    ? take((size_t)p.sep_splits_u * k2 * p.nxp * sizeof(float))
+                    : 0;
+  p.off_sep_p = (sep && op == CGH_OP_BACKWARD)
+                    ? take((size_t)p.sep_splits_p * k2 * p.nyp * sizeof(float))
+                    : 0;
   p.total = off;
   return p;
 }
@@ -78,8 +113,17 @@ Workspace carve(const Plan& p, void* base) {
   w.rec64 = p.op == CGH_OP_FORWARD_F64 ? (double4*)(b + p.off_rec64) : nullptr;
   w.ytab = (p.op == CGH_OP_FORWARD && p.variant == CGH_COMPENSATED) ? (float*)(b + p.off_ytab)
                                                                      : nullptr;
-  w.partial = p.op == CGH_OP_BACKWARD ? (float*)(b + p.off_partial) : nullptr;
-  w.gpad = (p.op == CGH_OP_BACKWARD && p.need_gpad) ? (float*)(b + p.off_gpad) : nullptr;
+  const bool direct_adj = p.op == CGH_OP_BACKWARD && p.variant != CGH_SEPARABLE;
+  w.partial = direct_adj ? (float*)(b + p.off_partial) : nullptr;
+  w.gpad = (direct_adj && p.need_gpad) ? (float*)(b + p.off_gpad) : nullptr;
+  const bool sep = p.variant == CGH_SEPARABLE && p.op != CGH_OP_FORWARD_F64;
+  w.sep_x = sep ? (float*)(b + p.off_sep_x) : nullptr;
+  w.sep_y = sep ? (float*)(b + p.off_sep_y) : nullptr;
+  w.sep_c = (sep && p.op == CGH_OP_FORWARD && p.sep_splits > 1) ? (float*)(b + p.off_sep_c)
+                                                                 : nullptr;
+  w.sep_g = (sep && p.op == CGH_OP_BACKWARD) ? (float*)(b + p.off_sep_g) : nullptr;
+  w.sep_u = (sep && p.op == CGH_OP_BACKWARD) ? (float*)(b + p.off_sep_u) : nullptr;
+  w.sep_p = (sep && p.op == CGH_OP_BACKWARD) ? (float*)(b + p.off_sep_p) : nullptr;
   return w;
 }
 
@@ -164,6 +208,56 @@ inline int hip_status(hipError_t e) { return e == hipSuccess ? CGH_OK : CGH_EHIP
 
 }  // namespace
 
+// ------------------------------------------------------------- separable --
+
+// I = P Q^T with P = (A cY, -A sY) [nyp][k2], Q = (cX, sX) [nxp][k2].
+int forward_separable(const Plan& p, const Workspace& w, float* hologram, hipStream_t s) {
+  hipError_t e = launch_sep_table(w.xrec, nullptr, p.npad, p.nx, p.nxp, w.sep_x, s);
+  if (e == hipSuccess) e = launch_sep_table(w.yrec, w.amp, p.npad, p.ny, p.nyp, w.sep_y, s);
+  if (e != hipSuccess) return CGH_EHIP;
+  const EventPair ev = profile_begin(CGH_KERNEL_FWD_SEPARABLE, s);
+  if (p.sep_splits == 1) {
+    e = launch_gemm_f32(true, true, w.sep_y, p.k2, w.sep_x, p.k2, hologram, p.nx, 0, p.nyp,
+                        p.nxp, (int)p.k2, 1, p.ny, p.nx, s);
+  } else {
+    const int64_t plane = (int64_t)p.nyp * p.nxp;
+    e = launch_gemm_f32(true, true, w.sep_y, p.k2, w.sep_x, p.k2, w.sep_c, p.nxp, plane, p.nyp,
+                        p.nxp, (int)p.k2, p.sep_splits, p.nyp, p.nxp, s);
+  }
+  profile_end(CGH_KERNEL_FWD_SEPARABLE, ev, s);
+  if (e != hipSuccess) return CGH_EHIP;
+  if (p.sep_splits > 1)
+    e = launch_sep_sum_slices(w.sep_c, p.sep_splits, (int64_t)p.nyp * p.nxp, p.nxp, p.nx, p.ny,
+                              hologram, s);
+  return hip_status(e);
+}
+
+// U = Y^T G (Y = (cY, sY) [nyp][k2]), Pm = X^T G^T (X = (cX, sX) [nxp][k2]),
+// then the per-point fold.
+int backward_separable(const Plan& p, const Workspace& w, const float* x, const float* y,
+                       const float* z, const float* a, double pitch, double wavelength,
+                       const float* g, float* gx, float* gy, float* gz, float* ga,
+                       hipStream_t s) {
+  hipError_t e = launch_sep_table(w.xrec, nullptr, p.npad, p.nx, p.nxp, w.sep_x, s);
+  if (e == hipSuccess) e = launch_sep_table(w.yrec, nullptr, p.npad, p.ny, p.nyp, w.sep_y, s);
+  if (e == hipSuccess) e = launch_sep_pad(g, p.nx, p.ny, p.nyp, p.nxp, w.sep_g, s);
+  if (e != hipSuccess) return CGH_EHIP;
+  const int64_t u_plane = p.k2 * p.nxp, p_plane = p.k2 * p.nyp;
+  const EventPair ev = profile_begin(CGH_KERNEL_ADJ_SEPARABLE, s);
+  // U[k][x] = sum_y Y[y][k] G[y][x]: A = Y stored [y][k], B = G stored [y][x].
+  e = launch_gemm_f32(false, false, w.sep_y, p.k2, w.sep_g, p.nxp, w.sep_u, p.nxp, u_plane,
+                      (int)p.k2, p.nxp, p.nyp, p.sep_splits_u, (int)p.k2, p.nxp, s);
+  // Pm[k][y] = sum_x X[x][k] G[y][x]: A = X stored [x][k], B = G stored [y][x].
+  if (e == hipSuccess)
+    e = launch_gemm_f32(false, true, w.sep_x, p.k2, w.sep_g, p.nxp, w.sep_p, p.nyp, p_plane,
+                        (int)p.k2, p.nyp, p.nxp, p.sep_splits_p, (int)p.k2, p.nyp, s);
+  profile_end(CGH_KERNEL_ADJ_SEPARABLE, ev, s);
+  if (e != hipSuccess) return CGH_EHIP;
+  e = launch_sep_fold(p, w, w.sep_u, p.sep_splits_u, u_plane, p.nxp, w.sep_p, p.sep_splits_p,
+                      p_plane, p.nyp, x, y, z, a, pitch, wavelength, gx, gy, gz, ga, s);
+  return hip_status(e);
+}
+
 }  // namespace cgh
 
 using namespace cgh;
@@ -172,7 +266,9 @@ extern "C" {
 
 size_t cgh_workspace_bytes(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   if (op != CGH_OP_FORWARD && op != CGH_OP_FORWARD_F64 && op != CGH_OP_BACKWARD) return 0;
-  if (op != CGH_OP_FORWARD_F64 && variant != CGH_PLAIN && variant != CGH_COMPENSATED) return 0;
+  if (op != CGH_OP_FORWARD_F64 && variant != CGH_PLAIN && variant != CGH_COMPENSATED &&
+      variant != CGH_SEPARABLE)
+    return 0;
   if (n < 0 || n > kMaxPoints || nx < 1 || ny < 1 || nx > kMaxSide || ny > kMaxSide) return 0;
   if (n == 0) return 0;
   return make_plan(n, nx, ny, variant, op).total;
@@ -183,7 +279,8 @@ int cgh_forward(const float* x, const float* y, const float* z, const float* a, 
                 float* hologram, void* workspace, size_t workspace_bytes, void* stream) {
   int rc = check_common(x, y, z, a, n, nx, ny, pitch, wavelength);
   if (rc) return rc;
-  if (variant != CGH_PLAIN && variant != CGH_COMPENSATED) return CGH_EINVAL;
+  if (variant != CGH_PLAIN && variant != CGH_COMPENSATED && variant != CGH_SEPARABLE)
+    return CGH_EINVAL;
   if (!hologram) return CGH_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   if (n == 0) return hip_status(launch_fill_zero_f32(hologram, (int64_t)nx * ny, s));
@@ -193,6 +290,7 @@ int cgh_forward(const float* x, const float* y, const float* z, const float* a, 
   const Workspace w = carve(p, workspace);
   hipError_t e = launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, false, s);
   if (e != hipSuccess) return CGH_EHIP;
+  if (variant == CGH_SEPARABLE) return forward_separable(p, w, hologram, s);
   if (variant == CGH_COMPENSATED) {
     e = launch_ytab(p, w, s);
     if (e != hipSuccess) return CGH_EHIP;
@@ -233,7 +331,8 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
                  float* grad_a, void* workspace, size_t workspace_bytes, void* stream) {
   int rc = check_common(x, y, z, a, n, nx, ny, pitch, wavelength);
   if (rc) return rc;
-  if (variant != CGH_PLAIN && variant != CGH_COMPENSATED) return CGH_EINVAL;
+  if (variant != CGH_PLAIN && variant != CGH_COMPENSATED && variant != CGH_SEPARABLE)
+    return CGH_EINVAL;
   if (!grad_hologram) return CGH_EINVAL;
   if (n > 0 && (!grad_x || !grad_y || !grad_z || !grad_a)) return CGH_EINVAL;
   if (n == 0) return CGH_OK;
@@ -244,6 +343,9 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
   const Workspace w = carve(p, workspace);
   hipError_t e = launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, false, s);
   if (e != hipSuccess) return CGH_EHIP;
+  if (variant == CGH_SEPARABLE)
+    return backward_separable(p, w, x, y, z, a, pitch, wavelength, grad_hologram, grad_x, grad_y,
+                              grad_z, grad_a, s);
   const float* g = grad_hologram;
   int64_t ldg = nx;
   if (p.need_gpad) {

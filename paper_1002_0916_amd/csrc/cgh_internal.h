@@ -110,6 +110,13 @@ struct Workspace {
   float* ytab;     // forward, compensated: [groups][npad][kCompRows]
   float* partial;  // adjoint: [regions][npad][4]
   float* gpad;     // adjoint: G copied to a [ny][nsx*kAdjCols] zero-padded grid
+  // separable variant (tables of k2 = 2 * npad floats per row / column)
+  float* sep_x;    // [nxp][k2]  (cX, sX) per point
+  float* sep_y;    // [nyp][k2]  forward: (A cY, -A sY); adjoint: (cY, sY)
+  float* sep_c;    // forward split-K planes [splits][nyp][nxp]
+  float* sep_g;    // adjoint: G zero-padded to [nyp][nxp]
+  float* sep_u;    // adjoint: [splits_u][k2][nxp]
+  float* sep_p;    // adjoint: [splits_p][k2][nyp]
 };
 
 struct Plan {
@@ -123,6 +130,10 @@ struct Plan {
   int32_t nsx, regions, ngroups;
   int64_t strip_rows;
   bool need_gpad;
+  // separable variant
+  int32_t nxp, nyp, sep_splits, sep_splits_u, sep_splits_p;
+  int64_t k2;
+  size_t off_sep_x, off_sep_y, off_sep_c, off_sep_g, off_sep_u, off_sep_p;
   size_t off_plain, off_amp, off_xrec, off_yrec, off_rec64, off_ytab, off_partial, off_gpad, total;
 };
 
@@ -140,6 +151,25 @@ hipError_t launch_fwd_plain(const Plan& p, const Workspace& w, float* out, hipSt
 hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s);
 hipError_t launch_fwd_f64(const Plan& p, const Workspace& w, double* out, hipStream_t s);
 hipError_t launch_pad_g(const Plan& p, const float* g, float* gpad, hipStream_t s);
+// FP32 matrix-core GEMM (gemm.hip): C[m][n] = sum_k A(m, k) B(n, k), split
+// over `splits` K slices written to C + z * slice_stride.  M, N multiples of
+// 128; K / splits a multiple of 32.
+hipError_t launch_gemm_f32(bool a_kcontig, bool b_kcontig, const float* A, int64_t lda,
+                           const float* B, int64_t ldb, float* C, int64_t ldc,
+                           int64_t slice_stride, int M, int N, int K, int splits, int m_valid,
+                           int n_valid, hipStream_t s);
+// Separable variant (separable.hip).
+hipError_t launch_sep_table(const float* rec, const float* amp, int64_t npad, int rows_valid,
+                            int rows_pad, float* tab, hipStream_t s);
+hipError_t launch_sep_sum_slices(const float* C, int splits, int64_t slice_stride, int64_t ldc,
+                                 int nx, int ny, float* out, hipStream_t s);
+hipError_t launch_sep_pad(const float* g, int nx, int ny, int rows_pad, int cols_pad, float* gp,
+                          hipStream_t s);
+hipError_t launch_sep_fold(const Plan& p, const Workspace& w, const float* U, int su,
+                           int64_t u_stride, int64_t ldu, const float* Pm, int sp, int64_t p_stride,
+                           int64_t ldp, const float* x, const float* y, const float* z,
+                           const float* a, double pitch, double wavelength, float* gx, float* gy,
+                           float* gz, float* ga, hipStream_t s);
 // Runs per point group for this launch (<= p.regions), from the occupancy of
 // the adjoint kernel on the current device.
 int adj_runs(const Plan& p);

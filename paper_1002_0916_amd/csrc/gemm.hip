@@ -1,0 +1,175 @@
+// FP32 matrix-core GEMM for the separable form of the hologram sum.
+//
+//   C[m][n] (+)= sum_k A(m, k) B(n, k)
+//
+// Each operand is stored either K-contiguous (element (m, k) at m * ld + k)
+// or M/N-contiguous (element (m, k) at k * ld + m).  The workgroup computes a
+// 128 x 128 tile of C with 4 waves, each a 64 x 64 quadrant made of 2 x 2
+// blocks of v_mfma_f32_32x32x2_f32 (lane l holds A[l % 32][l / 32] and
+// B[l / 32][l % 32]; accumulator register r of lane l is C[(r / 4) * 8 +
+// (l / 32) * 4 + r % 4][l % 32]).  K advances 32 at a time through
+// double-buffered LDS tiles stored [row][k] with rows padded to 36 floats;
+// within a stage, the MFMA at substep t takes k = t on lanes 0-31 and
+// k = 16 + t on lanes 32-63, so each lane reads 16 consecutive floats per
+// block (four 16-byte LDS reads).  Global loads of the next stage are issued
+// before the current stage's MFMAs.
+//
+// Split-K: blockIdx.z selects a contiguous K slice; slice z writes its own
+// C plane (C + z * slice_stride), summed afterwards in a fixed order.
+//
+// Shapes: M, N multiples of 128 and K (per slice) a multiple of 32, with the
+// operands zero-padded to those sizes; the store is masked to m < m_valid,
+// n < n_valid.
+#include "cgh_internal.h"
+
+namespace cgh {
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kBM = 128, kBN = 128, kBK = 32, kPitch = kBK + 4;
+constexpr int kGemmThreads = 256;
+
+// Loads this thread's share of a 128 x 32 operand tile (16 floats).
+template <bool KCONTIG>
+__device__ __forceinline__ void load_tile(const float* __restrict__ src, int64_t ld, int row0,
+                                          int k0, float4 (&r)[4]) {
+  const int t = threadIdx.x;
+  if (KCONTIG) {
+    // thread t: row t / 2, k half t % 2 (16 consecutive k)
+    const float* p = src + (int64_t)(row0 + t / 2) * ld + k0 + (t & 1) * 16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = *reinterpret_cast<const float4*>(p + 4 * q);
+  } else {
+    // thread t: k = t % 32, 16 consecutive rows starting at (t / 32) * 16
+    const float* p = src + (int64_t)(k0 + (t & 31)) * ld + row0 + (t >> 5) * 16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = *reinterpret_cast<const float4*>(p + 4 * q);
+  }
+}
+
+template <bool KCONTIG>
+__device__ __forceinline__ void store_tile(float* __restrict__ lds, const float4 (&r)[4]) {
+  const int t = threadIdx.x;
+  if (KCONTIG) {
+    float* p = lds + (t / 2) * kPitch + (t & 1) * 16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<float4*>(p + 4 * q) = r[q];
+  } else {
+    const int k = t & 31, m0 = (t >> 5) * 16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      lds[(m0 + 4 * q + 0) * kPitch + k] = r[q].x;
+      lds[(m0 + 4 * q + 1) * kPitch + k] = r[q].y;
+      lds[(m0 + 4 * q + 2) * kPitch + k] = r[q].z;
+      lds[(m0 + 4 * q + 3) * kPitch + k] = r[q].w;
+    }
+  }
+}
+
+template <bool AK, bool BK>
+__global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(
+    const float* __restrict__ A, int64_t lda, const float* __restrict__ B, int64_t ldb,
+    float* __restrict__ C, int64_t ldc, int64_t slice_stride, int k_slice, int m_valid,
+    int n_valid) {
+  __shared__ float As[2][kBM * kPitch];
+  __shared__ float Bs[2][kBN * kPitch];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int m0 = (int)(tile / gridDim.x) * kBM;
+  const int n0 = (int)(tile % gridDim.x) * kBN;
+  const int kbeg = blockIdx.z * k_slice;
+  const int nstages = k_slice / kBK;
+
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+  float4 ra[4], rb[4];
+  load_tile<AK>(A, lda, m0, kbeg, ra);
+  load_tile<BK>(B, ldb, n0, kbeg, rb);
+  store_tile<AK>(As[0], ra);
+  store_tile<BK>(Bs[0], rb);
+  __syncthreads();
+
+  const int kk = (lane >> 5) * 16;
+  for (int s = 0; s < nstages; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nstages) {
+      load_tile<AK>(A, lda, m0, kbeg + (s + 1) * kBK, ra);
+      load_tile<BK>(B, ldb, n0, kbeg + (s + 1) * kBK, rb);
+    }
+    float fa[2][16], fb[2][16];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float* pa = As[buf] + (wm * 64 + i * 32 + (lane & 31)) * kPitch + kk;
+      const float* pb = Bs[buf] + (wn * 64 + i * 32 + (lane & 31)) * kPitch + kk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 va = *reinterpret_cast<const float4*>(pa + 4 * q);
+        const float4 vb = *reinterpret_cast<const float4*>(pb + 4 * q);
+        fa[i][4 * q + 0] = va.x; fa[i][4 * q + 1] = va.y;
+        fa[i][4 * q + 2] = va.z; fa[i][4 * q + 3] = va.w;
+        fb[i][4 * q + 0] = vb.x; fb[i][4 * q + 1] = vb.y;
+        fb[i][4 * q + 2] = vb.z; fb[i][4 * q + 3] = vb.w;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i][t], fb[j][t], acc[i][j], 0, 0, 0);
+    if (s + 1 < nstages) {
+      store_tile<AK>(As[buf ^ 1], ra);
+      store_tile<BK>(Bs[buf ^ 1], rb);
+    }
+    __syncthreads();
+  }
+
+  float* Cz = C + (int64_t)blockIdx.z * slice_stride;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn * 64 + j * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wm * 64 + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        if (m < m_valid && n < n_valid) Cz[(int64_t)m * ldc + n] = acc[i][j][r];
+      }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_gemm_f32(bool a_kcontig, bool b_kcontig, const float* A, int64_t lda,
+                           const float* B, int64_t ldb, float* C, int64_t ldc,
+                           int64_t slice_stride, int M, int N, int K, int splits, int m_valid,
+                           int n_valid, hipStream_t s) {
+  const dim3 grid(N / kBN, M / kBM, splits);
+  const int k_slice = K / splits;
+  if (a_kcontig && b_kcontig)
+    hipLaunchKernelGGL((gemm_f32_kernel<true, true>), grid, dim3(kGemmThreads), 0, s, A, lda, B,
+                       ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid);
+  else if (!a_kcontig && !b_kcontig)
+    hipLaunchKernelGGL((gemm_f32_kernel<false, false>), grid, dim3(kGemmThreads), 0, s, A, lda,
+                       B, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid);
+  else if (!a_kcontig && b_kcontig)
+    hipLaunchKernelGGL((gemm_f32_kernel<false, true>), grid, dim3(kGemmThreads), 0, s, A, lda, B,
+                       ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid);
+  else
+    hipLaunchKernelGGL((gemm_f32_kernel<true, false>), grid, dim3(kGemmThreads), 0, s, A, lda, B,
+                       ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid);
+  return hipGetLastError();
+}
+
+}  // namespace cgh

@@ -1,0 +1,190 @@
+// Separable form of the hologram sum, evaluated as dense contractions on the
+// matrix cores.
+//
+// The phase of Eq. (1) (Section 1) separates exactly by axis,
+// theta_j(x_h, y_h) = 2 pi (X_j(x_h) + Y_j(y_h)) with X_j = Prev (x_h - x_j)^2
+// and Y_j = Prev (y_h - y_j)^2 (both formed by the compensated axis_phase), so
+// cos(theta) = cX cY - sX sY and
+//
+//   I[y][x] = sum_j A_j (cY_j(y) cX_j(x) - sY_j(y) sX_j(x)) = sum_k P[y][k] Q[x][k]
+//
+// with P[y][2j] = A_j cY_j(y), P[y][2j+1] = -A_j sY_j(y), Q[x][2j] = cX_j(x),
+// Q[x][2j+1] = sX_j(x): one real GEMM of size ny x nx x 2N.  The adjoint sums
+// (see adjoint.hip) factor the same way:
+//
+//   U_j(x) = sum_y G cY,  V_j(x) = sum_y G sY            (GEMM 2N x nx x ny)
+//   Pc_j(y) = sum_x G cX, Ps_j(y) = sum_x G sX           (GEMM 2N x ny x nx)
+//   Sc = sum_x (cX U - sX V);  column sums of G sin = sX U + cX V
+//   row sums of G sin = cY Ps + sY Pc
+//
+// and Sx, Sr (x part) and Sy, Sr (y part) fold those with dx, dx^2, dy, dy^2.
+// This changes the algorithm (no per-interaction cosine): the per-point
+// tables cost O(N (nx + ny)) transcendentals and the bulk is FP32 MFMA work.
+#include "cgh_internal.h"
+#include "phase.h"
+
+namespace cgh {
+
+namespace {
+
+// tab[h][2j], tab[h][2j+1] = (s0 cos 2 pi phi, s1 sin 2 pi phi), phi the axis
+// phase of point j at coordinate h; (s0, s1) = (1, 1), or (A_j, -A_j) when
+// amp is given.  Rows h >= rows_valid are zero.
+__global__ __launch_bounds__(256) void sep_table_kernel(const float* __restrict__ rec,
+                                                        const float* __restrict__ amp,
+                                                        int64_t npad, int rows_valid,
+                                                        int64_t total, float2* __restrict__ tab) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int64_t j = t % npad;
+  const int h = (int)(t / npad);
+  float2 v = make_float2(0.0f, 0.0f);
+  if (h < rows_valid) {
+    const float* r = rec + j * kAxisRec;
+    const float phi = axis_phase((float)h, r[0], r[1], r[2], r[3], r[4]);
+    const float c = cos_rev(phi), s = sin_rev(phi);
+    if (amp) {
+      const float A = amp[j];
+      v = make_float2(A * c, -(A * s));
+    } else {
+      v = make_float2(c, s);
+    }
+  }
+  tab[t] = v;
+}
+
+// I[y][x] = sum over split slices of C[s][y][x] (fixed order).
+__global__ __launch_bounds__(256) void sep_sum_slices_kernel(const float* __restrict__ C,
+                                                             int splits, int64_t slice_stride,
+                                                             int64_t ldc, int nx, int ny,
+                                                             float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nx * ny) return;
+  const int64_t y = t / nx;
+  const int x = (int)(t - y * nx);
+  const float* p = C + y * ldc + x;
+  float s = p[0];
+  for (int z = 1; z < splits; ++z) s += p[(int64_t)z * slice_stride];
+  out[t] = s;
+}
+
+// G copied into a zero-padded [rows_pad][cols_pad] grid.
+__global__ __launch_bounds__(256) void sep_pad_kernel(const float* __restrict__ g, int nx, int ny,
+                                                      int cols_pad, int64_t total,
+                                                      float* __restrict__ gp) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int64_t y = t / cols_pad;
+  const int x = (int)(t - y * cols_pad);
+  gp[t] = (x < nx && y < ny) ? g[y * nx + x] : 0.0f;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One wave per point: fold the contraction results into the four sums and
+// scale them into the gradients (fixed reduction order: lane-strided FP64
+// sums, then a butterfly over the 64 lanes).
+__global__ __launch_bounds__(256) void sep_fold_kernel(
+    const float* __restrict__ xrec, const float* __restrict__ yrec, const float* __restrict__ Uc,
+    int su, int64_t u_stride, int64_t ldu, const float* __restrict__ Pc, int sp,
+    int64_t p_stride, int64_t ldp, int64_t n, int nx, int ny, const float* __restrict__ x,
+    const float* __restrict__ y, const float* __restrict__ z, const float* __restrict__ a,
+    double pitch, double wavelength, float* __restrict__ gx, float* __restrict__ gy,
+    float* __restrict__ gz, float* __restrict__ ga) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;  // whole waves leave together
+  const float* rx = xrec + j * kAxisRec;
+  const float* ry = yrec + j * kAxisRec;
+  const float xj = x[j], yj = y[j];
+  double Sc = 0.0, Sx = 0.0, Sy = 0.0, Sr = 0.0;
+  const float* urow = Uc + (2 * j) * ldu;
+  for (int h = lane; h < nx; h += 64) {
+    float U = 0.0f, V = 0.0f;
+    for (int s = 0; s < su; ++s) {
+      U += urow[s * u_stride + h];
+      V += urow[s * u_stride + ldu + h];
+    }
+    const float phi = axis_phase((float)h, rx[0], rx[1], rx[2], rx[3], rx[4]);
+    const double c = cos_rev(phi), sn = sin_rev(phi);
+    Sc += c * U - sn * V;
+    const double sg = sn * U + c * V;
+    const double dx = (double)h - (double)xj;
+    Sx += dx * sg;
+    Sr += dx * dx * sg;
+  }
+  const float* prow = Pc + (2 * j) * ldp;
+  for (int h = lane; h < ny; h += 64) {
+    float Pcos = 0.0f, Psin = 0.0f;
+    for (int s = 0; s < sp; ++s) {
+      Pcos += prow[s * p_stride + h];
+      Psin += prow[s * p_stride + ldp + h];
+    }
+    const float phi = axis_phase((float)h, ry[0], ry[1], ry[2], ry[3], ry[4]);
+    const double c = cos_rev(phi), sn = sin_rev(phi);
+    const double sr = c * Psin + sn * Pcos;
+    const double dy = (double)h - (double)yj;
+    Sy += dy * sr;
+    Sr += dy * dy * sr;
+  }
+  Sc = wave_sum(Sc);
+  Sx = wave_sum(Sx);
+  Sy = wave_sum(Sy);
+  Sr = wave_sum(Sr);
+  if (lane == 0) {
+    const double zj = (double)z[j], aj = (double)a[j];
+    // P_j = pi p^2 / (lambda z_j), Section 1.
+    const double P = M_PI * pitch * pitch / (wavelength * zj);
+    ga[j] = (float)Sc;
+    gx[j] = (float)(2.0 * aj * P * Sx);
+    gy[j] = (float)(2.0 * aj * P * Sy);
+    gz[j] = (float)(aj * P / zj * Sr);
+  }
+}
+
+inline unsigned blocks_for(int64_t count, int threads) {
+  return (unsigned)((count + threads - 1) / threads);
+}
+
+}  // namespace
+
+hipError_t launch_sep_table(const float* rec, const float* amp, int64_t npad, int rows_valid,
+                            int rows_pad, float* tab, hipStream_t s) {
+  const int64_t total = (int64_t)rows_pad * npad;
+  hipLaunchKernelGGL(sep_table_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, rec, amp,
+                     npad, rows_valid, total, (float2*)tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_sum_slices(const float* C, int splits, int64_t slice_stride, int64_t ldc,
+                                 int nx, int ny, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(sep_sum_slices_kernel, dim3(blocks_for((int64_t)nx * ny, 256)), dim3(256), 0,
+                     s, C, splits, slice_stride, ldc, nx, ny, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_pad(const float* g, int nx, int ny, int rows_pad, int cols_pad, float* gp,
+                          hipStream_t s) {
+  const int64_t total = (int64_t)rows_pad * cols_pad;
+  hipLaunchKernelGGL(sep_pad_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, g, nx, ny,
+                     cols_pad, total, gp);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_fold(const Plan& p, const Workspace& w, const float* U, int su,
+                           int64_t u_stride, int64_t ldu, const float* Pm, int sp, int64_t p_stride,
+                           int64_t ldp, const float* x, const float* y, const float* z,
+                           const float* a, double pitch, double wavelength, float* gx, float* gy,
+                           float* gz, float* ga, hipStream_t s) {
+  hipLaunchKernelGGL(sep_fold_kernel, dim3(blocks_for(p.n, 4)), dim3(256), 0, s,
+                     (const float*)w.xrec, (const float*)w.yrec, U, su, u_stride, ldu, Pm, sp,
+                     p_stride, ldp, p.n, p.nx, p.ny, x, y, z, a, pitch, wavelength, gx, gy, gz,
+                     ga);
+  return hipGetLastError();
+}
+
+}  // namespace cgh

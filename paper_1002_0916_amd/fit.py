@@ -41,7 +41,7 @@ def fit(x, y, z, a, target, nx: int, ny: int, iters: int = 100, lr: float = 1e-2
     opt = torch.optim.Adam([a_p, zp], lr=lr)
     losses = []
     if time_kernels:
-        for k in range(B.KERNEL_ADJ_COMPENSATED + 1):
+        for k in range(B.KERNEL_ADJ_SEPARABLE + 1):
             B.profile_read(k)
         B.profile_enable(True)
     torch.cuda.synchronize()
@@ -63,9 +63,13 @@ def fit(x, y, z, a, target, nx: int, ny: int, iters: int = 100, lr: float = 1e-2
                     losses=[float(v) for v in torch.stack(losses).cpu()] if losses else [],
                     seconds=seconds, iterations=iters)
     if time_kernels:
-        comp = B.variant_id(variant) == B.COMPENSATED
-        nf, tf = B.profile_read(B.KERNEL_FWD_COMPENSATED if comp else B.KERNEL_FWD_PLAIN)
-        na, ta = B.profile_read(B.KERNEL_ADJ_COMPENSATED if comp else B.KERNEL_ADJ_PLAIN)
+        v = B.variant_id(variant)
+        fk = {B.PLAIN: B.KERNEL_FWD_PLAIN, B.COMPENSATED: B.KERNEL_FWD_COMPENSATED,
+              B.SEPARABLE: B.KERNEL_FWD_SEPARABLE}[v]
+        ak = {B.PLAIN: B.KERNEL_ADJ_PLAIN, B.COMPENSATED: B.KERNEL_ADJ_COMPENSATED,
+              B.SEPARABLE: B.KERNEL_ADJ_SEPARABLE}[v]
+        nf, tf = B.profile_read(fk)
+        na, ta = B.profile_read(ak)
         res.fwd_ms = tf / max(nf, 1)
         res.adj_ms = ta / max(na, 1)
     return res

@@ -15,7 +15,7 @@ from paper_1002_0916_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["plain", "compensated"]
+VARIANTS = ["plain", "compensated", "separable"]
 GROUPS = ("x", "y", "z", "a")
 
 

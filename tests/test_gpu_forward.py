@@ -17,7 +17,7 @@ from paper_1002_0916_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["plain", "compensated"]
+VARIANTS = ["plain", "compensated", "separable"]
 
 
 def run(cloud, nx, ny, variant, dev, pitch=W.PITCH, wl=W.WAVELENGTH):
@@ -135,8 +135,10 @@ def test_f64_kernel_mesh_sampled(oracle_mod):
     assert err <= 1e-11
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", ["plain", "compensated"])
 def test_eightfold_symmetry_bitwise(variant):
+    """(The separable variant multiplies A into the row table, so swapping x
+    and y reorders a product: equal in exact arithmetic, not bitwise.)"""
     dev = device()
     c = W.Cloud(*[np.array([v], dtype=np.float32) for v in (50.0, 60.0, 0.41, 0.9)])
     I = run(c, 101, 121, variant, dev)
@@ -192,3 +194,16 @@ def test_kernel_profiling_counts_launches():
     n, ms = B.profile_read(B.KERNEL_FWD_COMPENSATED)
     assert n == 3 and ms > 0
     assert B.profile_read(B.KERNEL_FWD_COMPENSATED) == (0, 0.0)
+
+
+def test_separable_symmetry_to_rounding():
+    dev = device()
+    c = W.Cloud(*[np.array([v], dtype=np.float32) for v in (50.0, 60.0, 0.41, 0.9)])
+    I = run(c, 101, 121, "separable", dev)
+    x0, y0 = 50, 60
+    for u in range(0, 51):
+        for v in range(0, 51):
+            vals = np.array([I[y0 + v, x0 + u], I[y0 + v, x0 - u], I[y0 - v, x0 + u],
+                             I[y0 - v, x0 - u], I[y0 + u, x0 + v], I[y0 + u, x0 - v],
+                             I[y0 - u, x0 + v], I[y0 - u, x0 - v]])
+            assert np.ptp(vals) <= 4e-7, (u, v, vals)
