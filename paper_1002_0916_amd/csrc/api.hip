@@ -22,12 +22,12 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Split-K count for a GEMM of `tiles` 128 x 128 output tiles and contraction
-// length k (a multiple of 128): double it while the grid stays within about
-// 1024 workgroups (two rounds of two per CU), each slice keeps >= 256 of k,
-// and slices stay multiples of 32.
+// length k (a multiple of 128): double it while the grid stays within one
+// round of resident GEMM workgroups (two per CU on 256 CUs), each slice keeps
+// >= 256 of k, and slices stay multiples of 32.
 inline int gemm_splits(int64_t tiles, int64_t k) {
   int s = 1;
-  while (tiles * s * 2 <= 1024 && (k / 32) % (s * 2) == 0 && k / (s * 2) >= 256) s *= 2;
+  while (tiles * s * 2 <= 512 && (k / 32) % (s * 2) == 0 && k / (s * 2) >= 256) s *= 2;
   return s;
 }
 

@@ -31,45 +31,55 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 constexpr int kBM = 128, kBN = 128, kBK = 32, kPitch = kBK + 4;
 constexpr int kGemmThreads = 256;
 
-// Loads this thread's share of a 128 x 32 operand tile (16 floats).
+// This thread's share of a 128 x 32 operand tile (16 floats), kept in named
+// registers (no array, so nothing is ever placed in scratch memory).
+struct Frag16 {
+  float4 q0, q1, q2, q3;
+};
+
 template <bool KCONTIG>
-__device__ __forceinline__ void load_tile(const float* __restrict__ src, int64_t ld, int row0,
-                                          int k0, float4 (&r)[4]) {
+__device__ __forceinline__ Frag16 load_tile(const float* __restrict__ src, int64_t ld, int row0,
+                                            int k0) {
   const int t = threadIdx.x;
-  if (KCONTIG) {
-    // thread t: row t / 2, k half t % 2 (16 consecutive k)
-    const float* p = src + (int64_t)(row0 + t / 2) * ld + k0 + (t & 1) * 16;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = *reinterpret_cast<const float4*>(p + 4 * q);
-  } else {
-    // thread t: k = t % 32, 16 consecutive rows starting at (t / 32) * 16
-    const float* p = src + (int64_t)(k0 + (t & 31)) * ld + row0 + (t >> 5) * 16;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = *reinterpret_cast<const float4*>(p + 4 * q);
-  }
+  // K-contiguous: thread t takes row t / 2 and the k half t % 2 (16 consecutive
+  // k); M/N-contiguous: k = t % 32 and 16 consecutive rows from (t / 32) * 16.
+  const float* p = KCONTIG ? src + (int64_t)(row0 + t / 2) * ld + k0 + (t & 1) * 16
+                           : src + (int64_t)(k0 + (t & 31)) * ld + row0 + (t >> 5) * 16;
+  Frag16 r;
+  r.q0 = *reinterpret_cast<const float4*>(p + 0);
+  r.q1 = *reinterpret_cast<const float4*>(p + 4);
+  r.q2 = *reinterpret_cast<const float4*>(p + 8);
+  r.q3 = *reinterpret_cast<const float4*>(p + 12);
+  return r;
+}
+
+__device__ __forceinline__ void store_col(float* lds, int m, int k, float4 v) {
+  lds[(m + 0) * kPitch + k] = v.x;
+  lds[(m + 1) * kPitch + k] = v.y;
+  lds[(m + 2) * kPitch + k] = v.z;
+  lds[(m + 3) * kPitch + k] = v.w;
 }
 
 template <bool KCONTIG>
-__device__ __forceinline__ void store_tile(float* __restrict__ lds, const float4 (&r)[4]) {
+__device__ __forceinline__ void store_tile(float* __restrict__ lds, const Frag16& r) {
   const int t = threadIdx.x;
   if (KCONTIG) {
     float* p = lds + (t / 2) * kPitch + (t & 1) * 16;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) *reinterpret_cast<float4*>(p + 4 * q) = r[q];
+    *reinterpret_cast<float4*>(p + 0) = r.q0;
+    *reinterpret_cast<float4*>(p + 4) = r.q1;
+    *reinterpret_cast<float4*>(p + 8) = r.q2;
+    *reinterpret_cast<float4*>(p + 12) = r.q3;
   } else {
     const int k = t & 31, m0 = (t >> 5) * 16;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      lds[(m0 + 4 * q + 0) * kPitch + k] = r[q].x;
-      lds[(m0 + 4 * q + 1) * kPitch + k] = r[q].y;
-      lds[(m0 + 4 * q + 2) * kPitch + k] = r[q].z;
-      lds[(m0 + 4 * q + 3) * kPitch + k] = r[q].w;
-    }
+    store_col(lds, m0 + 0, k, r.q0);
+    store_col(lds, m0 + 4, k, r.q1);
+    store_col(lds, m0 + 8, k, r.q2);
+    store_col(lds, m0 + 12, k, r.q3);
   }
 }
 
 template <bool AK, bool BK>
-__global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(
+__global__ __launch_bounds__(kGemmThreads, 2) void gemm_f32_kernel(
     const float* __restrict__ A, int64_t lda, const float* __restrict__ B, int64_t ldb,
     float* __restrict__ C, int64_t ldc, int64_t slice_stride, int k_slice, int m_valid,
     int n_valid) {
@@ -92,9 +102,8 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-  float4 ra[4], rb[4];
-  load_tile<AK>(A, lda, m0, kbeg, ra);
-  load_tile<BK>(B, ldb, n0, kbeg, rb);
+  Frag16 ra = load_tile<AK>(A, lda, m0, kbeg);
+  Frag16 rb = load_tile<BK>(B, ldb, n0, kbeg);
   store_tile<AK>(As[0], ra);
   store_tile<BK>(Bs[0], rb);
   __syncthreads();
@@ -103,8 +112,8 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_f32_kernel(
   for (int s = 0; s < nstages; ++s) {
     const int buf = s & 1;
     if (s + 1 < nstages) {
-      load_tile<AK>(A, lda, m0, kbeg + (s + 1) * kBK, ra);
-      load_tile<BK>(B, ldb, n0, kbeg + (s + 1) * kBK, rb);
+      ra = load_tile<AK>(A, lda, m0, kbeg + (s + 1) * kBK);
+      rb = load_tile<BK>(B, ldb, n0, kbeg + (s + 1) * kBK);
     }
     float fa[2][16], fb[2][16];
 #pragma unroll

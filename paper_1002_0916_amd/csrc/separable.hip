@@ -85,9 +85,11 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// One wave per point: fold the contraction results into the four sums and
-// scale them into the gradients (fixed reduction order: lane-strided FP64
-// sums, then a butterfly over the 64 lanes).
+// One workgroup (4 waves) per point: waves 0-1 fold the x part (columns
+// h = 64 k + lane, k even / odd), waves 2-3 the y part (rows, likewise).  Each
+// wave adds its terms in FP64 in a fixed lane-strided order and reduces them
+// with a butterfly; the workgroup then combines the four wave sums in a fixed
+// order and scales them into the gradients.
 __global__ __launch_bounds__(256) void sep_fold_kernel(
     const float* __restrict__ xrec, const float* __restrict__ yrec, const float* __restrict__ Uc,
     int su, int64_t u_stride, int64_t ldu, const float* __restrict__ Pc, int sp,
@@ -95,47 +97,63 @@ __global__ __launch_bounds__(256) void sep_fold_kernel(
     const float* __restrict__ y, const float* __restrict__ z, const float* __restrict__ a,
     double pitch, double wavelength, float* __restrict__ gx, float* __restrict__ gy,
     float* __restrict__ gz, float* __restrict__ ga) {
+  __shared__ double part[4][3];
   const int lane = threadIdx.x & 63;
-  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= n) return;  // whole waves leave together
-  const float* rx = xrec + j * kAxisRec;
-  const float* ry = yrec + j * kAxisRec;
-  const float xj = x[j], yj = y[j];
-  double Sc = 0.0, Sx = 0.0, Sy = 0.0, Sr = 0.0;
-  const float* urow = Uc + (2 * j) * ldu;
-  for (int h = lane; h < nx; h += 64) {
-    float U = 0.0f, V = 0.0f;
-    for (int s = 0; s < su; ++s) {
-      U += urow[s * u_stride + h];
-      V += urow[s * u_stride + ldu + h];
+  const int wave = threadIdx.x >> 6;
+  const int64_t j = blockIdx.x;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (wave < 2) {
+    // x part: Sc, Sx, Sr_x
+    const float* rx = xrec + j * kAxisRec;
+    const double xj = (double)x[j];
+    const float* urow = Uc + (2 * j) * ldu;
+    for (int h = lane + 64 * wave; h < nx; h += 128) {
+      float U = 0.0f, V = 0.0f;
+      for (int s = 0; s < su; ++s) {
+        U += urow[s * u_stride + h];
+        V += urow[s * u_stride + ldu + h];
+      }
+      const float phi = axis_phase((float)h, rx[0], rx[1], rx[2], rx[3], rx[4]);
+      const double c = cos_rev(phi), sn = sin_rev(phi);
+      s0 += c * U - sn * V;
+      const double sg = sn * U + c * V;
+      const double dx = (double)h - xj;
+      s1 += dx * sg;
+      s2 += dx * dx * sg;
     }
-    const float phi = axis_phase((float)h, rx[0], rx[1], rx[2], rx[3], rx[4]);
-    const double c = cos_rev(phi), sn = sin_rev(phi);
-    Sc += c * U - sn * V;
-    const double sg = sn * U + c * V;
-    const double dx = (double)h - (double)xj;
-    Sx += dx * sg;
-    Sr += dx * dx * sg;
-  }
-  const float* prow = Pc + (2 * j) * ldp;
-  for (int h = lane; h < ny; h += 64) {
-    float Pcos = 0.0f, Psin = 0.0f;
-    for (int s = 0; s < sp; ++s) {
-      Pcos += prow[s * p_stride + h];
-      Psin += prow[s * p_stride + ldp + h];
+  } else {
+    // y part: Sy, Sr_y
+    const float* ry = yrec + j * kAxisRec;
+    const double yj = (double)y[j];
+    const float* prow = Pc + (2 * j) * ldp;
+    for (int h = lane + 64 * (wave - 2); h < ny; h += 128) {
+      float Pcos = 0.0f, Psin = 0.0f;
+      for (int s = 0; s < sp; ++s) {
+        Pcos += prow[s * p_stride + h];
+        Psin += prow[s * p_stride + ldp + h];
+      }
+      const float phi = axis_phase((float)h, ry[0], ry[1], ry[2], ry[3], ry[4]);
+      const double c = cos_rev(phi), sn = sin_rev(phi);
+      const double sr = c * Psin + sn * Pcos;
+      const double dy = (double)h - yj;
+      s1 += dy * sr;
+      s2 += dy * dy * sr;
     }
-    const float phi = axis_phase((float)h, ry[0], ry[1], ry[2], ry[3], ry[4]);
-    const double c = cos_rev(phi), sn = sin_rev(phi);
-    const double sr = c * Psin + sn * Pcos;
-    const double dy = (double)h - (double)yj;
-    Sy += dy * sr;
-    Sr += dy * dy * sr;
   }
-  Sc = wave_sum(Sc);
-  Sx = wave_sum(Sx);
-  Sy = wave_sum(Sy);
-  Sr = wave_sum(Sr);
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
   if (lane == 0) {
+    part[wave][0] = s0;
+    part[wave][1] = s1;
+    part[wave][2] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double Sc = part[0][0] + part[1][0];
+    const double Sx = part[0][1] + part[1][1];
+    const double Sy = part[2][1] + part[3][1];
+    const double Sr = (part[0][2] + part[1][2]) + (part[2][2] + part[3][2]);
     const double zj = (double)z[j], aj = (double)a[j];
     // P_j = pi p^2 / (lambda z_j), Section 1.
     const double P = M_PI * pitch * pitch / (wavelength * zj);
@@ -180,7 +198,7 @@ hipError_t launch_sep_fold(const Plan& p, const Workspace& w, const float* U, in
                            int64_t ldp, const float* x, const float* y, const float* z,
                            const float* a, double pitch, double wavelength, float* gx, float* gy,
                            float* gz, float* ga, hipStream_t s) {
-  hipLaunchKernelGGL(sep_fold_kernel, dim3(blocks_for(p.n, 4)), dim3(256), 0, s,
+  hipLaunchKernelGGL(sep_fold_kernel, dim3((unsigned)p.n), dim3(256), 0, s,
                      (const float*)w.xrec, (const float*)w.yrec, U, su, u_stride, ldu, Pm, sp,
                      p_stride, ldp, p.n, p.nx, p.ny, x, y, z, a, pitch, wavelength, gx, gy, gz,
                      ga);
