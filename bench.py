@@ -46,15 +46,25 @@ SLOTS = {
 # cores (dense MFMA FP32 peak 157.3 TFLOP/s): the forward is one GEMM of
 # 2 x (2N) flops per pixel (4 flops per interaction), the adjoint two
 # (8 flops per interaction).
+# The half-precision separable variants run the same GEMMs on the fp16/bf16
+# matrix cores (dense peak 2.5 PFLOP/s); f16x3 issues three MFMAs per product
+# (hi*hi, hi*lo, lo*hi), so its matrix-core work is three times the flops.
 PEAK_MFMA_F32 = 157.3e12
-MFMA_FLOPS = {"fwd_separable": 4, "adj_separable": 8}
+PEAK_MFMA_F16 = 2.5e15
+MFMA_FLOPS = {"separable": (4, 8, PEAK_MFMA_F32), "separable_f16x3": (12, 24, PEAK_MFMA_F16),
+              "separable_f16": (4, 8, PEAK_MFMA_F16), "separable_bf16": (4, 8, PEAK_MFMA_F16)}
+ALL_VARIANTS = ("compensated", "plain", "separable", "separable_f16x3", "separable_f16",
+                "separable_bf16")
 
 
 def peak_interactions(key):
-    """Roofline peak (interactions/s) of a kernel: VALU issue for the direct
-    variants, FP32 matrix cores for the separable one."""
-    if key in MFMA_FLOPS:
-        return PEAK_MFMA_F32 / MFMA_FLOPS[key]
+    """Roofline peak (interactions/s) of a kernel ("fwd_<variant>" or
+    "adj_<variant>"): VALU issue for the direct variants, the matrix cores of
+    the GEMM operand type for the separable ones."""
+    op, variant = key.split("_", 1)
+    if variant in MFMA_FLOPS:
+        f_fwd, f_adj, peak = MFMA_FLOPS[variant]
+        return peak / (f_fwd if op == "fwd" else f_adj)
     return PEAK_SLOTS / SLOTS[key]
 
 
@@ -64,7 +74,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--variant", default="compensated",
-                    choices=["compensated", "plain", "separable"])
+                    choices=list(ALL_VARIANTS))
     ap.add_argument("--cpu-seconds", type=float, default=8.0,
                     help="target wall seconds of each oracle sample (forward, adjoint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -115,8 +125,10 @@ def measured_traffic(kernel):
     return rec["traffic_bytes"]
 
 
-FWD_KERNEL = {"plain": 0, "compensated": 1, "separable": 5}
-ADJ_KERNEL = {"plain": 3, "compensated": 4, "separable": 6}
+FWD_KERNEL = {"plain": 0, "compensated": 1}
+ADJ_KERNEL = {"plain": 3, "compensated": 4}
+for _v in ALL_VARIANTS[2:]:
+    FWD_KERNEL[_v], ADJ_KERNEL[_v] = 5, 6
 
 
 def timed_steps(step, steps, torch):
@@ -179,13 +191,13 @@ def main():
         return step
 
     results = {}
-    others = [v for v in ("compensated", "plain", "separable") if v != args.variant]
+    others = [v for v in ALL_VARIANTS if v != args.variant]
     for variant in [args.variant] + others:
         step = make_step(variant)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        for k in range(5):
+        for k in range(B.KERNEL_ADJ_SEPARABLE + 1):
             B.profile_read(k)  # clear
         B.profile_enable(True)
         ms, wall = timed_steps(step, args.steps, torch)
@@ -198,13 +210,21 @@ def main():
                                 adj_kernel_ms=ta_ / max(na, 1), fwd_launches=nf,
                                 adj_launches=na)
 
-    # Accuracy of the FP32 forward variants against the FP64 GPU forward.
+    # Accuracy of every forward variant against the FP64 GPU forward, and of
+    # every adjoint against the compensated one (relative L2 per gradient
+    # group, the largest of the four), with G = I64 - T.
     I64 = B.forward_f64(x, y, z, a, nx, ny)
     suma = float(np.sum(np.abs(cloud.a.astype(np.float64))))
-    errs = {}
-    for variant in ("plain", "compensated", "separable"):
+    errs, adj_errs = {}, {}
+    G64 = (I64 - T.double()).float()
+    ref = [t.double() for t in B.backward(x, y, z, a, G64, nx, ny, wl.pitch, wl.wavelength,
+                                         "compensated")]
+    for variant in ALL_VARIANTS:
         Iv = B.forward(x, y, z, a, nx, ny, wl.pitch, wl.wavelength, variant)
         errs[variant] = float((Iv.double() - I64).abs().max().item()) / suma
+        gv = B.backward(x, y, z, a, G64, nx, ny, wl.pitch, wl.wavelength, variant)
+        adj_errs[variant] = max(float((g.double() - r).norm() / r.norm())
+                                for g, r in zip(gv, ref))
     torch.cuda.synchronize()
 
     main_r = results[args.variant]
@@ -229,6 +249,7 @@ def main():
             "adj_roofline_frac": (inter / (r["adj_kernel_ms"] * 1e-3)) /
                                  peak_interactions("adj_" + variant),
             "max_err_vs_fp64_over_sum_abs_a": errs[variant],
+            "adj_rel_l2_vs_compensated": adj_errs[variant],
         }
 
     out = {
@@ -254,17 +275,19 @@ def main():
         },
         "roofline": {
             "kernel": adj_key,
-            "bound": "mfma" if args.variant == "separable" else "alu",
+            "bound": "mfma" if args.variant.startswith("separable") else "alu",
             "achieved": achieved,
             "peak": peak,
             "unit": "Ginteraction/s",
             "frac": achieved / peak,
-            "traffic": measured_traffic("adj_partial_kernel<%d>"
-                                        % (1 if args.variant == "compensated" else 0)),
+            "traffic": (None if args.variant.startswith("separable") else
+                        measured_traffic("adj_partial_kernel<%d>"
+                                         % (1 if args.variant == "compensated" else 0))),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                             "copy-calibrated)",
             "slots_per_interaction": SLOTS.get(adj_key),
-            "flops_per_interaction": MFMA_FLOPS.get(adj_key),
+            "flops_per_interaction": (MFMA_FLOPS[args.variant][1]
+                                      if args.variant in MFMA_FLOPS else None),
             "peak_slots_per_s": PEAK_SLOTS,
             "kernel_ms": adj_ms,
         },
@@ -387,7 +410,7 @@ def _clouds(name, W):
 
 def report_workload(args):
     """One JSON report line for a non-headline workload: forward kernel times
-    and errors against the FP64 GPU forward for both FP32 variants, the adjoint
+    and errors against the FP64 GPU forward for every variant, the adjoint
     kernel times, and for fit4k the Adam fitting loop."""
     import numpy as np
     import torch
@@ -412,10 +435,8 @@ def report_workload(args):
     torch.cuda.synchronize()
     out["fwd_f64_ms"] = (time.perf_counter() - t64) * 1e3
     out["fwd_f64_gpps"] = inter / (out["fwd_f64_ms"] * 1e-3) / 1e9
-    for variant, fk, ak in (("plain", B.KERNEL_FWD_PLAIN, B.KERNEL_ADJ_PLAIN),
-                            ("compensated", B.KERNEL_FWD_COMPENSATED,
-                             B.KERNEL_ADJ_COMPENSATED),
-                            ("separable", B.KERNEL_FWD_SEPARABLE, B.KERNEL_ADJ_SEPARABLE)):
+    for variant in ALL_VARIANTS:
+        fk, ak = FWD_KERNEL[variant], ADJ_KERNEL[variant]
         Iv = B.forward(x, y, z, a, nx, ny, wl.pitch, wl.wavelength, variant)
         err = float((Iv.double() - I64).abs().max().item()) / suma
         fms = _kernel_ms(B, torch, lambda: B.forward(x, y, z, a, nx, ny, wl.pitch,

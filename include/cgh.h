@@ -52,6 +52,17 @@
  *                       the forward and adjoint run as FP32 matrix-core GEMMs.
  *                       Needs a larger workspace (tables of 2N floats per row
  *                       and per column, plus split-K partial planes).
+ *      CGH_SEPARABLE_F16X3, CGH_SEPARABLE_F16, CGH_SEPARABLE_BF16
+ *                       CGH_SEPARABLE with the contractions on the fp16 / bf16
+ *                       matrix cores (FP32 accumulation).  The tables and G are
+ *                       rounded to 16 bits after dividing A_j (forward) or G
+ *                       (adjoint) by a power of two >= their largest
+ *                       magnitude (undone exactly on the FP32 result).  F16X3
+ *                       splits each operand into fp16 hi + lo and forms
+ *                       hi*hi + hi*lo + lo*hi (near-FP32 accuracy); F16 and
+ *                       BF16 round each operand once (unit roundoff 2^-11 and
+ *                       2^-8), so the forward error stays below about
+ *                       2 u sum |A_j| (u = 2^-11, 2^-8).
  *    FP64 appears only in the per-point precompute of P_j / (2 pi) and its
  *    hi/lo split (and in cgh_forward_f64).
  */
@@ -75,6 +86,9 @@ extern "C" {
 #define CGH_PLAIN 0
 #define CGH_COMPENSATED 1
 #define CGH_SEPARABLE 2
+#define CGH_SEPARABLE_F16X3 3
+#define CGH_SEPARABLE_F16 4
+#define CGH_SEPARABLE_BF16 5
 
 /* Operations, for cgh_workspace_bytes. */
 #define CGH_OP_FORWARD 0
@@ -87,7 +101,7 @@ extern "C" {
 #define CGH_KERNEL_FWD_F64 2
 #define CGH_KERNEL_ADJ_PLAIN 3
 #define CGH_KERNEL_ADJ_COMPENSATED 4
-#define CGH_KERNEL_FWD_SEPARABLE 5 /* the forward GEMM */
+#define CGH_KERNEL_FWD_SEPARABLE 5 /* the forward GEMM (every separable variant) */
 #define CGH_KERNEL_ADJ_SEPARABLE 6 /* both adjoint GEMMs, one event pair */
 #define CGH_KERNEL_COUNT 7
 
@@ -106,7 +120,8 @@ size_t cgh_workspace_bytes(int64_t n, int32_t nx, int32_t ny, int32_t variant, i
  *                and amplitudes A_j.
  *   hologram     device float32[ny][nx], overwritten with I.  n = 0 writes
  *                zeros.
- *   variant      CGH_PLAIN, CGH_COMPENSATED or CGH_SEPARABLE.
+ *   variant      CGH_PLAIN, CGH_COMPENSATED, CGH_SEPARABLE or one of the
+ *                half-precision separable variants.
  */
 int cgh_forward(const float* x, const float* y, const float* z, const float* a, int64_t n,
                 int32_t nx, int32_t ny, double pitch, double wavelength, int32_t variant,
@@ -140,7 +155,8 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
 /* Human-readable text for a status code (static storage, never NULL). */
 const char* cgh_strerror(int status);
 
-/* Library ABI version (major * 100 + minor). */
+/* Library ABI version (major * 100 + minor): 101 adds the half-precision
+ * separable variants. */
 int cgh_version(void);
 
 /*

@@ -31,6 +31,24 @@ inline int gemm_splits(int64_t tiles, int64_t k) {
   return s;
 }
 
+inline bool valid_variant(int32_t v) { return v >= CGH_PLAIN && v <= CGH_SEPARABLE_BF16; }
+
+// The 16-bit GEMM format of a half-precision separable variant, or -1.
+inline int half_mode(int32_t v) {
+  switch (v) {
+    case CGH_SEPARABLE_F16X3:
+      return kHalfF16x3;
+    case CGH_SEPARABLE_F16:
+      return kHalfF16;
+    case CGH_SEPARABLE_BF16:
+      return kHalfBF16;
+    default:
+      return -1;
+  }
+}
+
+inline bool is_separable(int32_t v) { return v == CGH_SEPARABLE || half_mode(v) >= 0; }
+
 }  // namespace
 
 Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
@@ -78,27 +96,33 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   p.off_ytab = (op == CGH_OP_FORWARD && variant == CGH_COMPENSATED)
                    ? take((size_t)p.groups * np * kCompRows * sizeof(float))
                    : 0;
-  const bool direct_adj = op == CGH_OP_BACKWARD && variant != CGH_SEPARABLE;
+  const bool direct_adj = op == CGH_OP_BACKWARD && !is_separable(variant);
   p.off_partial = direct_adj ? take((size_t)p.regions * np * sizeof(float4)) : 0;
   p.off_gpad = (direct_adj && p.need_gpad)
                    ? take((size_t)p.nsx * kAdjCols * (size_t)ny * sizeof(float))
                    : 0;
-  const bool sep = variant == CGH_SEPARABLE && op != CGH_OP_FORWARD_F64;
+  const bool sep = is_separable(variant) && op != CGH_OP_FORWARD_F64;
+  const bool f32 = sep && variant == CGH_SEPARABLE;
+  const int hm = sep ? half_mode(variant) : -1;
+  const bool fwd = op == CGH_OP_FORWARD, bwd = op == CGH_OP_BACKWARD;
   const size_t k2 = (size_t)p.k2;
-  p.off_sep_x = sep ? take((size_t)p.nxp * k2 * sizeof(float)) : 0;
-  p.off_sep_y = sep ? take((size_t)p.nyp * k2 * sizeof(float)) : 0;
-  p.off_sep_c = (sep && op == CGH_OP_FORWARD && p.sep_splits > 1)
-                    ? take((size_t)p.sep_splits * p.nyp * (size_t)p.nxp * sizeof(float))
+  const size_t nxp = (size_t)p.nxp, nyp = (size_t)p.nyp;
+  p.off_sep_x = f32 ? take(nxp * k2 * sizeof(float)) : 0;
+  p.off_sep_y = f32 ? take(nyp * k2 * sizeof(float)) : 0;
+  p.off_sep_g = (f32 && bwd) ? take(nyp * nxp * sizeof(float)) : 0;
+  p.off_sep_c = (sep && fwd && p.sep_splits > 1)
+                    ? take((size_t)p.sep_splits * nyp * nxp * sizeof(float))
                     : 0;
-  p.off_sep_g = (sep && op == CGH_OP_BACKWARD)
-                    ? take((size_t)p.nyp * (size_t)p.nxp * sizeof(float))
-                    : 0;
-  p.off_sep_u = (sep && op == CGH_OP_BACKWARD)
-                    ? take((size_t)p.sep_splits_u * k2 * p.nxp * sizeof(float))
-                    : 0;
-  p.off_sep_p = (sep && op == CGH_OP_BACKWARD)
-                    ? take((size_t)p.sep_splits_p * k2 * p.nyp * sizeof(float))
-                    : 0;
+  p.off_sep_u = (sep && bwd) ? take((size_t)p.sep_splits_u * k2 * nxp * sizeof(float)) : 0;
+  p.off_sep_p = (sep && bwd) ? take((size_t)p.sep_splits_p * k2 * nyp * sizeof(float)) : 0;
+  // 16-bit planes: hi, then (f16x3) lo at the next 256-byte boundary.
+  const size_t planes = hm == kHalfF16x3 ? 2 : 1;
+  auto take_planes = [&](size_t elems) { return take(planes * align256(elems * 2)); };
+  p.off_hx = hm >= 0 ? take_planes(nxp * k2) : 0;
+  p.off_hy = hm >= 0 ? take_planes(nyp * k2) : 0;
+  p.off_hg = (hm >= 0 && bwd) ? take_planes(nyp * nxp) : 0;
+  p.off_hgt = (hm >= 0 && bwd) ? take_planes(nyp * nxp) : 0;
+  p.off_hmax = hm >= 0 ? take(sizeof(unsigned)) : 0;
   p.total = off;
   return p;
 }
@@ -113,17 +137,34 @@ Workspace carve(const Plan& p, void* base) {
   w.rec64 = p.op == CGH_OP_FORWARD_F64 ? (double4*)(b + p.off_rec64) : nullptr;
   w.ytab = (p.op == CGH_OP_FORWARD && p.variant == CGH_COMPENSATED) ? (float*)(b + p.off_ytab)
                                                                      : nullptr;
-  const bool direct_adj = p.op == CGH_OP_BACKWARD && p.variant != CGH_SEPARABLE;
+  const bool direct_adj = p.op == CGH_OP_BACKWARD && !is_separable(p.variant);
   w.partial = direct_adj ? (float*)(b + p.off_partial) : nullptr;
   w.gpad = (direct_adj && p.need_gpad) ? (float*)(b + p.off_gpad) : nullptr;
-  const bool sep = p.variant == CGH_SEPARABLE && p.op != CGH_OP_FORWARD_F64;
-  w.sep_x = sep ? (float*)(b + p.off_sep_x) : nullptr;
-  w.sep_y = sep ? (float*)(b + p.off_sep_y) : nullptr;
-  w.sep_c = (sep && p.op == CGH_OP_FORWARD && p.sep_splits > 1) ? (float*)(b + p.off_sep_c)
-                                                                 : nullptr;
-  w.sep_g = (sep && p.op == CGH_OP_BACKWARD) ? (float*)(b + p.off_sep_g) : nullptr;
-  w.sep_u = (sep && p.op == CGH_OP_BACKWARD) ? (float*)(b + p.off_sep_u) : nullptr;
-  w.sep_p = (sep && p.op == CGH_OP_BACKWARD) ? (float*)(b + p.off_sep_p) : nullptr;
+  const bool sep = is_separable(p.variant) && p.op != CGH_OP_FORWARD_F64;
+  const bool f32 = sep && p.variant == CGH_SEPARABLE;
+  const int hm = sep ? half_mode(p.variant) : -1;
+  const bool fwd = p.op == CGH_OP_FORWARD, bwd = p.op == CGH_OP_BACKWARD;
+  w.sep_x = f32 ? (float*)(b + p.off_sep_x) : nullptr;
+  w.sep_y = f32 ? (float*)(b + p.off_sep_y) : nullptr;
+  w.sep_g = (f32 && bwd) ? (float*)(b + p.off_sep_g) : nullptr;
+  w.sep_c = (sep && fwd && p.sep_splits > 1) ? (float*)(b + p.off_sep_c) : nullptr;
+  w.sep_u = (sep && bwd) ? (float*)(b + p.off_sep_u) : nullptr;
+  w.sep_p = (sep && bwd) ? (float*)(b + p.off_sep_p) : nullptr;
+  if (hm >= 0) {
+    const size_t k2 = (size_t)p.k2, nxp = (size_t)p.nxp, nyp = (size_t)p.nyp;
+    const bool split = hm == kHalfF16x3;
+    auto planes = [&](size_t off, size_t elems, uint16_t*& hi, uint16_t*& lo) {
+      hi = (uint16_t*)(b + off);
+      lo = split ? (uint16_t*)(b + off + align256(elems * 2)) : nullptr;
+    };
+    planes(p.off_hx, nxp * k2, w.hx_hi, w.hx_lo);
+    planes(p.off_hy, nyp * k2, w.hy_hi, w.hy_lo);
+    if (bwd) {
+      planes(p.off_hg, nyp * nxp, w.hg_hi, w.hg_lo);
+      planes(p.off_hgt, nyp * nxp, w.hgt_hi, w.hgt_lo);
+    }
+    w.hmax = (unsigned*)(b + p.off_hmax);
+  }
   return w;
 }
 
@@ -258,6 +299,69 @@ int backward_separable(const Plan& p, const Workspace& w, const float* x, const 
   return hip_status(e);
 }
 
+// Half-precision separable variants: the same contractions on 16-bit planes
+// (A_j, resp. G, divided by a power of two recorded in w.hmax).
+int forward_separable_half(const Plan& p, const Workspace& w, float* hologram, hipStream_t s) {
+  const int hm = half_mode(p.variant);
+  hipError_t e = launch_absmax(w.amp, p.npad, w.hmax, s);
+  if (e == hipSuccess)
+    e = launch_sep_table_half(hm, w.xrec, nullptr, nullptr, p.npad, p.nx, p.nxp, false, w.hx_hi,
+                              w.hx_lo, s);
+  if (e == hipSuccess)
+    e = launch_sep_table_half(hm, w.yrec, w.amp, w.hmax, p.npad, p.ny, p.nyp, false, w.hy_hi,
+                              w.hy_lo, s);
+  if (e != hipSuccess) return CGH_EHIP;
+  const EventPair ev = profile_begin(CGH_KERNEL_FWD_SEPARABLE, s);
+  if (p.sep_splits == 1) {
+    e = launch_gemm_half(hm, w.hy_hi, w.hy_lo, p.k2, w.hx_hi, w.hx_lo, p.k2, hologram, p.nx, 0,
+                         p.nyp, p.nxp, (int)p.k2, 1, p.ny, p.nx, w.hmax, s);
+  } else {
+    const int64_t plane = (int64_t)p.nyp * p.nxp;
+    e = launch_gemm_half(hm, w.hy_hi, w.hy_lo, p.k2, w.hx_hi, w.hx_lo, p.k2, w.sep_c, p.nxp,
+                         plane, p.nyp, p.nxp, (int)p.k2, p.sep_splits, p.nyp, p.nxp, w.hmax, s);
+  }
+  profile_end(CGH_KERNEL_FWD_SEPARABLE, ev, s);
+  if (e != hipSuccess) return CGH_EHIP;
+  if (p.sep_splits > 1)
+    e = launch_sep_sum_slices(w.sep_c, p.sep_splits, (int64_t)p.nyp * p.nxp, p.nxp, p.nx, p.ny,
+                              hologram, s);
+  return hip_status(e);
+}
+
+int backward_separable_half(const Plan& p, const Workspace& w, const float* x, const float* y,
+                            const float* z, const float* a, double pitch, double wavelength,
+                            const float* g, float* gx, float* gy, float* gz, float* ga,
+                            hipStream_t s) {
+  const int hm = half_mode(p.variant);
+  hipError_t e = launch_absmax(g, (int64_t)p.nx * p.ny, w.hmax, s);
+  if (e == hipSuccess)
+    e = launch_sep_table_half(hm, w.xrec, nullptr, nullptr, p.npad, p.nx, p.nxp, true, w.hx_hi,
+                              w.hx_lo, s);
+  if (e == hipSuccess)
+    e = launch_sep_table_half(hm, w.yrec, nullptr, nullptr, p.npad, p.ny, p.nyp, true, w.hy_hi,
+                              w.hy_lo, s);
+  if (e == hipSuccess)
+    e = launch_sep_pad_half(hm, g, p.nx, p.ny, p.nyp, p.nxp, w.hmax, w.hg_hi, w.hg_lo, w.hgt_hi,
+                            w.hgt_lo, s);
+  if (e != hipSuccess) return CGH_EHIP;
+  const int64_t u_plane = p.k2 * p.nxp, p_plane = p.k2 * p.nyp;
+  const EventPair ev = profile_begin(CGH_KERNEL_ADJ_SEPARABLE, s);
+  // U[k][x] = sum_y Yt[k][y] Gt[x][y]
+  e = launch_gemm_half(hm, w.hy_hi, w.hy_lo, p.nyp, w.hgt_hi, w.hgt_lo, p.nyp, w.sep_u, p.nxp,
+                       u_plane, (int)p.k2, p.nxp, p.nyp, p.sep_splits_u, (int)p.k2, p.nxp, w.hmax,
+                       s);
+  // Pm[k][y] = sum_x Xt[k][x] G[y][x]
+  if (e == hipSuccess)
+    e = launch_gemm_half(hm, w.hx_hi, w.hx_lo, p.nxp, w.hg_hi, w.hg_lo, p.nxp, w.sep_p, p.nyp,
+                         p_plane, (int)p.k2, p.nyp, p.nxp, p.sep_splits_p, (int)p.k2, p.nyp,
+                         w.hmax, s);
+  profile_end(CGH_KERNEL_ADJ_SEPARABLE, ev, s);
+  if (e != hipSuccess) return CGH_EHIP;
+  e = launch_sep_fold(p, w, w.sep_u, p.sep_splits_u, u_plane, p.nxp, w.sep_p, p.sep_splits_p,
+                      p_plane, p.nyp, x, y, z, a, pitch, wavelength, gx, gy, gz, ga, s);
+  return hip_status(e);
+}
+
 }  // namespace cgh
 
 using namespace cgh;
@@ -266,9 +370,7 @@ extern "C" {
 
 size_t cgh_workspace_bytes(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   if (op != CGH_OP_FORWARD && op != CGH_OP_FORWARD_F64 && op != CGH_OP_BACKWARD) return 0;
-  if (op != CGH_OP_FORWARD_F64 && variant != CGH_PLAIN && variant != CGH_COMPENSATED &&
-      variant != CGH_SEPARABLE)
-    return 0;
+  if (op != CGH_OP_FORWARD_F64 && !valid_variant(variant)) return 0;
   if (n < 0 || n > kMaxPoints || nx < 1 || ny < 1 || nx > kMaxSide || ny > kMaxSide) return 0;
   if (n == 0) return 0;
   return make_plan(n, nx, ny, variant, op).total;
@@ -279,8 +381,7 @@ int cgh_forward(const float* x, const float* y, const float* z, const float* a, 
                 float* hologram, void* workspace, size_t workspace_bytes, void* stream) {
   int rc = check_common(x, y, z, a, n, nx, ny, pitch, wavelength);
   if (rc) return rc;
-  if (variant != CGH_PLAIN && variant != CGH_COMPENSATED && variant != CGH_SEPARABLE)
-    return CGH_EINVAL;
+  if (!valid_variant(variant)) return CGH_EINVAL;
   if (!hologram) return CGH_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   if (n == 0) return hip_status(launch_fill_zero_f32(hologram, (int64_t)nx * ny, s));
@@ -291,6 +392,7 @@ int cgh_forward(const float* x, const float* y, const float* z, const float* a, 
   hipError_t e = launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, false, s);
   if (e != hipSuccess) return CGH_EHIP;
   if (variant == CGH_SEPARABLE) return forward_separable(p, w, hologram, s);
+  if (half_mode(variant) >= 0) return forward_separable_half(p, w, hologram, s);
   if (variant == CGH_COMPENSATED) {
     e = launch_ytab(p, w, s);
     if (e != hipSuccess) return CGH_EHIP;
@@ -331,8 +433,7 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
                  float* grad_a, void* workspace, size_t workspace_bytes, void* stream) {
   int rc = check_common(x, y, z, a, n, nx, ny, pitch, wavelength);
   if (rc) return rc;
-  if (variant != CGH_PLAIN && variant != CGH_COMPENSATED && variant != CGH_SEPARABLE)
-    return CGH_EINVAL;
+  if (!valid_variant(variant)) return CGH_EINVAL;
   if (!grad_hologram) return CGH_EINVAL;
   if (n > 0 && (!grad_x || !grad_y || !grad_z || !grad_a)) return CGH_EINVAL;
   if (n == 0) return CGH_OK;
@@ -346,6 +447,9 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
   if (variant == CGH_SEPARABLE)
     return backward_separable(p, w, x, y, z, a, pitch, wavelength, grad_hologram, grad_x, grad_y,
                               grad_z, grad_a, s);
+  if (half_mode(variant) >= 0)
+    return backward_separable_half(p, w, x, y, z, a, pitch, wavelength, grad_hologram, grad_x,
+                                   grad_y, grad_z, grad_a, s);
   const float* g = grad_hologram;
   int64_t ldg = nx;
   if (p.need_gpad) {
@@ -380,7 +484,7 @@ const char* cgh_strerror(int status) {
   }
 }
 
-int cgh_version(void) { return 100; }
+int cgh_version(void) { return 101; }
 
 int cgh_profile_enable(int32_t on) {
   Profiler& P = profiler();

@@ -117,6 +117,12 @@ struct Workspace {
   float* sep_g;    // adjoint: G zero-padded to [nyp][nxp]
   float* sep_u;    // adjoint: [splits_u][k2][nxp]
   float* sep_p;    // adjoint: [splits_p][k2][nyp]
+  // half-precision separable variants: 16-bit planes (hi, lo) and scales
+  uint16_t *hx_hi, *hx_lo;   // forward [nxp][k2]; adjoint transposed [k2][nxp]
+  uint16_t *hy_hi, *hy_lo;   // forward [nyp][k2] (with A); adjoint [k2][nyp]
+  uint16_t *hg_hi, *hg_lo;   // adjoint: G [nyp][nxp]
+  uint16_t *hgt_hi, *hgt_lo; // adjoint: G^T [nxp][nyp]
+  unsigned* hmax;            // largest |A| (forward) or |G| (adjoint), as float bits
 };
 
 struct Plan {
@@ -134,6 +140,7 @@ struct Plan {
   int32_t nxp, nyp, sep_splits, sep_splits_u, sep_splits_p;
   int64_t k2;
   size_t off_sep_x, off_sep_y, off_sep_c, off_sep_g, off_sep_u, off_sep_p;
+  size_t off_hx, off_hy, off_hg, off_hgt, off_hmax;  // half variants (hi plane; lo follows)
   size_t off_plain, off_amp, off_xrec, off_yrec, off_rec64, off_ytab, off_partial, off_gpad, total;
 };
 
@@ -170,6 +177,37 @@ hipError_t launch_sep_fold(const Plan& p, const Workspace& w, const float* U, in
                            int64_t ldp, const float* x, const float* y, const float* z,
                            const float* a, double pitch, double wavelength, float* gx, float* gy,
                            float* gz, float* ga, hipStream_t s);
+// Half-precision matrix-core GEMM (gemm_half.hip), K-contiguous 16-bit
+// planes; formats:
+constexpr int kHalfF16 = 0;    // one fp16 plane per operand
+constexpr int kHalfBF16 = 1;   // one bf16 plane per operand
+constexpr int kHalfF16x3 = 2;  // fp16 hi + lo planes, hi*hi + hi*lo + lo*hi
+hipError_t launch_gemm_half(int mode, const uint16_t* Ah, const uint16_t* Al, int64_t lda,
+                            const uint16_t* Bh, const uint16_t* Bl, int64_t ldb, float* C,
+                            int64_t ldc, int64_t slice_stride, int M, int N, int K, int splits,
+                            int m_valid, int n_valid, const unsigned* scale_max, hipStream_t s);
+
+// Power-of-two scale 2^e >= m for the largest magnitude m, given as the bits
+// of the non-negative float m (1 when m is 0 or not finite).  Dividing an
+// operand by it maps it into [-1, 1] exactly (only the exponent changes).
+__device__ __forceinline__ float pow2_scale(unsigned max_bits) {
+  const float m = __uint_as_float(max_bits);
+  if (!(m > 0.0f) || !(m < 3.0e38f)) return 1.0f;
+  int e;
+  const float f = frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
+  (void)f;
+  return ldexpf(1.0f, e);
+}
+
+// Separable variants with half-precision contractions (separable.hip).
+hipError_t launch_absmax(const float* v, int64_t count, unsigned* out, hipStream_t s);
+hipError_t launch_sep_table_half(int mode, const float* rec, const float* amp,
+                                 const unsigned* amp_max, int64_t npad, int rows_valid,
+                                 int rows_pad, bool transposed, uint16_t* hi, uint16_t* lo,
+                                 hipStream_t s);
+hipError_t launch_sep_pad_half(int mode, const float* g, int nx, int ny, int nyp, int nxp,
+                               const unsigned* g_max, uint16_t* gh, uint16_t* gl, uint16_t* gth,
+                               uint16_t* gtl, hipStream_t s);
 // Runs per point group for this launch (<= p.regions), from the occupancy of
 // the adjoint kernel on the current device.
 int adj_runs(const Plan& p);

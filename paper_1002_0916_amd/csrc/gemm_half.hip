@@ -1,0 +1,194 @@
+// Half-precision matrix-core GEMM for the separable form (FP32 accumulate).
+//
+//   C[m][n] = sum_k A(m, k) B(n, k),  A and B stored K-contiguous as 16-bit
+//   planes [rows][ld] (element (m, k) at m * ld + k).
+//
+// Formats (template MODE):
+//   kHalfF16    one fp16 plane per operand, one MFMA per product;
+//   kHalfBF16   one bf16 plane per operand;
+//   kHalfF16x3  hi and lo fp16 planes per operand (value = hi + lo) and three
+//               MFMAs per product, hi*hi + hi*lo + lo*hi: about 22 significant
+//               bits, close to FP32, at the fp16 matrix-core rate.
+//
+// v_mfma_f32_32x32x16_{f16,bf16}: lane l holds A[l % 32][(l / 32) * 8 + i]
+// and B[(l / 32) * 8 + i][l % 32] (i = 0..7, one 16-byte register quad), and
+// accumulator register r of lane l is C[(r / 4) * 8 + (l / 32) * 4 + r % 4]
+// [l % 32] (layout checked on the device).  The workgroup computes a 128 x 128
+// tile with 4 waves (64 x 64 each = 2 x 2 blocks); K advances 32 per stage
+// through double-buffered LDS tiles [row][k] with rows padded to 40 elements
+// (80 bytes: the 16-byte fragment reads of 16 consecutive lanes hit distinct
+// banks).  Split-K over blockIdx.z as in the FP32 kernel.  M, N multiples of
+// 128; K per slice a multiple of 32; stores masked to m < m_valid, n < n_valid.
+#include <stdint.h>
+
+#include "cgh_internal.h"
+
+namespace cgh {
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kHBM = 128, kHBN = 128, kHBK = 32, kHPitch = kHBK + 8;
+constexpr int kHThreads = 256;
+
+// 16 consecutive k of one row: this thread's share of a 128 x 32 plane tile.
+struct Half16 {
+  uint4 lo8, hi8;  // elements k0..k0+7, k0+8..k0+15
+};
+
+__device__ __forceinline__ Half16 load_plane(const uint16_t* __restrict__ src, int64_t ld, int row0,
+                                             int k0) {
+  const int t = threadIdx.x;
+  const uint16_t* p = src + (int64_t)(row0 + t / 2) * ld + k0 + (t & 1) * 16;
+  Half16 r;
+  r.lo8 = *reinterpret_cast<const uint4*>(p);
+  r.hi8 = *reinterpret_cast<const uint4*>(p + 8);
+  return r;
+}
+
+__device__ __forceinline__ void store_plane(uint16_t* __restrict__ lds, const Half16& r) {
+  const int t = threadIdx.x;
+  uint16_t* p = lds + (t / 2) * kHPitch + (t & 1) * 16;
+  *reinterpret_cast<uint4*>(p) = r.lo8;
+  *reinterpret_cast<uint4*>(p + 8) = r.hi8;
+}
+
+template <int MODE>
+__device__ __forceinline__ floatx16 mma(uint4 a, uint4 b, floatx16 c) {
+  if (MODE == kHalfBF16)
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(halfx8, a),
+                                                __builtin_bit_cast(halfx8, b), c, 0, 0, 0);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kHThreads, 2) void gemm_half_kernel(
+    const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al, int64_t lda,
+    const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl, int64_t ldb,
+    float* __restrict__ C, int64_t ldc, int64_t slice_stride, int k_slice, int m_valid,
+    int n_valid, const unsigned* __restrict__ scale_max) {
+  constexpr bool kSplit = MODE == kHalfF16x3;
+  constexpr int kPlane = kHBM * kHPitch;
+  // [buffer][plane]: A hi, B hi, and (split) A lo, B lo
+  __shared__ uint16_t smem[2][kSplit ? 4 : 2][kPlane];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int m0 = (int)(tile / gridDim.x) * kHBM;
+  const int n0 = (int)(tile % gridDim.x) * kHBN;
+  const int kbeg = blockIdx.z * k_slice;
+  const int nstages = k_slice / kHBK;
+
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+  Half16 rah = load_plane(Ah, lda, m0, kbeg);
+  Half16 rbh = load_plane(Bh, ldb, n0, kbeg);
+  Half16 ral, rbl;
+  if (kSplit) {
+    ral = load_plane(Al, lda, m0, kbeg);
+    rbl = load_plane(Bl, ldb, n0, kbeg);
+  }
+  store_plane(smem[0][0], rah);
+  store_plane(smem[0][1], rbh);
+  if (kSplit) {
+    store_plane(smem[0][2], ral);
+    store_plane(smem[0][3], rbl);
+  }
+  __syncthreads();
+
+  const int kq = (lane >> 5) * 8;
+  for (int s = 0; s < nstages; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nstages) {
+      const int kn = kbeg + (s + 1) * kHBK;
+      rah = load_plane(Ah, lda, m0, kn);
+      rbh = load_plane(Bh, ldb, n0, kn);
+      if (kSplit) {
+        ral = load_plane(Al, lda, m0, kn);
+        rbl = load_plane(Bl, ldb, n0, kn);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kHBK / 16; ++t) {
+      uint4 fah[2], fbh[2], fal[2], fbl[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int ra = (wm * 64 + i * 32 + (lane & 31)) * kHPitch + t * 16 + kq;
+        const int rb = (wn * 64 + i * 32 + (lane & 31)) * kHPitch + t * 16 + kq;
+        fah[i] = *reinterpret_cast<const uint4*>(&smem[buf][0][ra]);
+        fbh[i] = *reinterpret_cast<const uint4*>(&smem[buf][1][rb]);
+        if (kSplit) {
+          fal[i] = *reinterpret_cast<const uint4*>(&smem[buf][2][ra]);
+          fbl[i] = *reinterpret_cast<const uint4*>(&smem[buf][3][rb]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = mma<MODE>(fah[i], fbh[j], acc[i][j]);
+          if (kSplit) {
+            acc[i][j] = mma<MODE>(fah[i], fbl[j], acc[i][j]);
+            acc[i][j] = mma<MODE>(fal[i], fbh[j], acc[i][j]);
+          }
+        }
+    }
+    if (s + 1 < nstages) {
+      store_plane(smem[buf ^ 1][0], rah);
+      store_plane(smem[buf ^ 1][1], rbh);
+      if (kSplit) {
+        store_plane(smem[buf ^ 1][2], ral);
+        store_plane(smem[buf ^ 1][3], rbl);
+      }
+    }
+    __syncthreads();
+  }
+
+  // Undo the power-of-two operand scaling (exact).
+  const float alpha = scale_max ? pow2_scale(*scale_max) : 1.0f;
+  float* Cz = C + (int64_t)blockIdx.z * slice_stride;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn * 64 + j * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wm * 64 + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        if (m < m_valid && n < n_valid) Cz[(int64_t)m * ldc + n] = alpha * acc[i][j][r];
+      }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_gemm_half(int mode, const uint16_t* Ah, const uint16_t* Al, int64_t lda,
+                            const uint16_t* Bh, const uint16_t* Bl, int64_t ldb, float* C,
+                            int64_t ldc, int64_t slice_stride, int M, int N, int K, int splits,
+                            int m_valid, int n_valid, const unsigned* scale_max, hipStream_t s) {
+  const dim3 grid(N / kHBN, M / kHBM, splits);
+  const int k_slice = K / splits;
+  if (mode == kHalfF16x3)
+    hipLaunchKernelGGL(gemm_half_kernel<kHalfF16x3>, grid, dim3(kHThreads), 0, s, Ah, Al, lda,
+                       Bh, Bl, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, scale_max);
+  else if (mode == kHalfBF16)
+    hipLaunchKernelGGL(gemm_half_kernel<kHalfBF16>, grid, dim3(kHThreads), 0, s, Ah, Al, lda,
+                       Bh, Bl, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, scale_max);
+  else
+    hipLaunchKernelGGL(gemm_half_kernel<kHalfF16>, grid, dim3(kHThreads), 0, s, Ah, Al, lda, Bh,
+                       Bl, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, scale_max);
+  return hipGetLastError();
+}
+
+}  // namespace cgh

@@ -64,10 +64,11 @@ def fit(x, y, z, a, target, nx: int, ny: int, iters: int = 100, lr: float = 1e-2
                     seconds=seconds, iterations=iters)
     if time_kernels:
         v = B.variant_id(variant)
-        fk = {B.PLAIN: B.KERNEL_FWD_PLAIN, B.COMPENSATED: B.KERNEL_FWD_COMPENSATED,
-              B.SEPARABLE: B.KERNEL_FWD_SEPARABLE}[v]
-        ak = {B.PLAIN: B.KERNEL_ADJ_PLAIN, B.COMPENSATED: B.KERNEL_ADJ_COMPENSATED,
-              B.SEPARABLE: B.KERNEL_ADJ_SEPARABLE}[v]
+        sep = v in B.SEPARABLE_IDS
+        fk = B.KERNEL_FWD_SEPARABLE if sep else {B.PLAIN: B.KERNEL_FWD_PLAIN,
+                                                 B.COMPENSATED: B.KERNEL_FWD_COMPENSATED}[v]
+        ak = B.KERNEL_ADJ_SEPARABLE if sep else {B.PLAIN: B.KERNEL_ADJ_PLAIN,
+                                                 B.COMPENSATED: B.KERNEL_ADJ_COMPENSATED}[v]
         nf, tf = B.profile_read(fk)
         na, ta = B.profile_read(ak)
         res.fwd_ms = tf / max(nf, 1)

@@ -6,11 +6,25 @@ import torch
 
 from paper_1002_0916_amd import workloads as W
 
+# Unit roundoff of the 16-bit GEMM operand formats (11 and 8 significant bits).
+U_F16, U_BF16 = 2.0 ** -11, 2.0 ** -8
+
+
+def _half_fwd_bar(u):
+    """Forward bar of a once-rounded 16-bit format: every table entry carries a
+    relative error <= u, so a term A_j (cY cX - sY sX) is off by at most
+    (2u + u^2) |A_j| (|cY cX| + |sY sX| <= 1), i.e. |dI| <= (2u + u^2) sum |A|,
+    plus the FP32 bar for the phase and accumulation arithmetic."""
+    return 2 * u + u * u + 1e-4
+
+
 # Acceptance bars for the forward, as fractions of sum_j |A_j|: max |dI| over
 # the compared pixels.
-TOL_FWD = {"plain": 2e-3, "compensated": 1e-4, "separable": 1e-4}
+TOL_FWD = {"plain": 2e-3, "compensated": 1e-4, "separable": 1e-4, "separable_f16x3": 1e-4,
+           "separable_f16": _half_fwd_bar(U_F16), "separable_bf16": _half_fwd_bar(U_BF16)}
 # Relative L2 error bars per gradient group (A, x, y, z), same G on both sides.
-TOL_ADJ = {"plain": 1e-3, "compensated": 1e-4, "separable": 1e-4}
+TOL_ADJ = {"plain": 1e-3, "compensated": 1e-4, "separable": 1e-4, "separable_f16x3": 1e-4,
+           "separable_f16": 2 * U_F16, "separable_bf16": 2 * U_BF16}
 
 
 def say(*args):

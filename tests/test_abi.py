@@ -64,7 +64,10 @@ def test_workspace_bytes(lib):
     assert f(-1, 16, 16, B.PLAIN, B.OP_FORWARD) == 0
     assert f(10, 0, 16, B.PLAIN, B.OP_FORWARD) == 0
     assert f(10, 16, 16, 7, B.OP_FORWARD) == 0
-    assert f(10, 16, 16, B.SEPARABLE, B.OP_FORWARD) > 0
+    for v in B.SEPARABLE_IDS:
+        assert f(10, 16, 16, v, B.OP_FORWARD) > 0
+        assert f(10, 16, 16, v, B.OP_BACKWARD) > 0
+    assert f(10, 16, 16, 6, B.OP_FORWARD) == 0
     assert f(10, 16, 16, B.PLAIN, 9) == 0
     assert f(4000001, 16, 16, B.PLAIN, B.OP_FORWARD) == 0
     assert f(4000000, 16, 16, B.PLAIN, B.OP_BACKWARD) > 0
@@ -108,7 +111,7 @@ def test_forward_rejects_bad_arguments(lib, case):
     elif case == "nan":
         args["pitch"] = float("nan")
     elif case == "variant":
-        args["v"] = 3
+        args["v"] = 6
     elif case == "out":
         args["out"] = None
     elif case == "toolarge":
@@ -153,7 +156,7 @@ def test_backward_rejects_bad_arguments(lib):
         rc = lib.cgh_backward(p, p, p, p, 10, 32, 32, 8e-6, 633e-9, B.PLAIN, args["gh"],
                               args["gx"], args["gy"], args["gz"], args["ga"], p, 1 << 30, None)
         assert rc == B.CGH_EINVAL, k
-    rc = lib.cgh_backward(p, p, p, p, 10, 32, 32, 8e-6, 633e-9, 3, p, p, p, p, p, p, 1 << 30,
+    rc = lib.cgh_backward(p, p, p, p, 10, 32, 32, 8e-6, 633e-9, 6, p, p, p, p, p, p, 1 << 30,
                           None)
     assert rc == B.CGH_EINVAL
     # n = 0 is a valid no-op that enqueues nothing

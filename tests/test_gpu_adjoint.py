@@ -15,7 +15,8 @@ from paper_1002_0916_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["plain", "compensated", "separable"]
+VARIANTS = ["plain", "compensated", "separable", "separable_f16x3", "separable_f16",
+            "separable_bf16"]
 GROUPS = ("x", "y", "z", "a")
 
 
@@ -115,6 +116,22 @@ def test_autograd_function_matches_backward(variant):
     ref = B.backward(*(t.detach() for t in (x, y, z, a)), Wt, 120, 80, variant=variant)
     for t, r in zip((x, y, z, a), ref):
         assert torch.equal(t.grad, r)
+
+
+@pytest.mark.parametrize("variant", ["separable_f16x3", "separable_f16", "separable_bf16"])
+@pytest.mark.parametrize("scale", [1e6, 1e-6])
+def test_half_variants_gradient_range(oracle_mod, variant, scale):
+    """G far outside the fp16 range or deep in its subnormals: the power-of-two
+    scaling of G keeps the gradients at the bar."""
+    nx, ny, n = 120, 90, 70
+    dev = device()
+    c = W.random_cloud(210, n, nx, ny, zlo=0.2, zhi=1.0, alo=-1.0, ahi=1.0, margin=20)
+    G = (upstream_gradient(oracle_mod, nx, ny, 310) * scale).astype(np.float32)
+    say("adjoint", variant, "G scale", scale)
+    gg = gpu_grads(c, G, nx, ny, variant, dev)
+    ref = oracle_mod.adjoint(*c.astuple(), nx, ny, G, threads=0)
+    assert all(np.all(np.isfinite(g)) for g in gg)
+    compare(gg, ref, variant, "scaled")
 
 
 def test_adjoint_workload_against_central_differences(oracle_mod):

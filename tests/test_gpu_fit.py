@@ -11,7 +11,7 @@ from paper_1002_0916_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("variant", ["compensated", "plain"])
+@pytest.mark.parametrize("variant", ["compensated", "plain", "separable_f16x3"])
 def test_fit_reduces_loss(variant):
     dev = device()
     nx, ny = 160, 120

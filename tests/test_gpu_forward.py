@@ -17,7 +17,8 @@ from paper_1002_0916_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["plain", "compensated", "separable"]
+VARIANTS = ["plain", "compensated", "separable", "separable_f16x3", "separable_f16",
+            "separable_bf16"]
 
 
 def run(cloud, nx, ny, variant, dev, pitch=W.PITCH, wl=W.WAVELENGTH):
@@ -207,3 +208,22 @@ def test_separable_symmetry_to_rounding():
                              I[y0 - v, x0 - u], I[y0 + u, x0 + v], I[y0 + u, x0 - v],
                              I[y0 - u, x0 + v], I[y0 - u, x0 - v]])
             assert np.ptp(vals) <= 4e-7, (u, v, vals)
+
+
+HALF = ["separable_f16x3", "separable_f16", "separable_bf16"]
+
+
+@pytest.mark.parametrize("variant", HALF)
+@pytest.mark.parametrize("scale", [1e6, 1e-6])
+def test_half_variants_amplitude_range(oracle_mod, variant, scale):
+    """Amplitudes far outside the fp16 range (1e6) or deep in its subnormals
+    (1e-6): the power-of-two operand scaling keeps the error at the bar."""
+    dev = device()
+    c = W.random_cloud(44, 200, 150, 110, alo=-1.0, ahi=1.0, margin=15)
+    c = W.Cloud(c.x, c.y, c.z, (c.a * scale).astype(np.float32))
+    I = run(c, 150, 110, variant, dev)
+    ref = oracle_mod.forward(*c.astuple(), 150, 110, threads=0)
+    err = max_err_frac(I, ref, c)
+    say(variant, "scale", scale, "max|dI|/sum|A| =", err)
+    assert np.all(np.isfinite(I))
+    assert err <= TOL_FWD[variant]
