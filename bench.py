@@ -42,6 +42,16 @@ SLOTS = {
     "adj_plain": 6 + 2 * TRANS_SLOTS,
     "adj_compensated": 4 + 2 * TRANS_SLOTS,
 }
+# The same work if every packable FP32 add/mul/fma ran as packed math (two
+# lanes per slot; fract and the transcendentals do not pack).  Packed FP32 is
+# disabled for all device code here, so this stricter bound is reported beside
+# the primary (non-packed) one, not instead of it.
+SLOTS_PACKED = {
+    "fwd_plain": 4 / 2 + 1 + TRANS_SLOTS,
+    "fwd_compensated": 2 / 2 + TRANS_SLOTS,
+    "adj_plain": 5 / 2 + 1 + 2 * TRANS_SLOTS,
+    "adj_compensated": 4 / 2 + 2 * TRANS_SLOTS,
+}
 # The separable variant is a different algorithm, bound by the FP32 matrix
 # cores (dense MFMA FP32 peak 157.3 TFLOP/s): the forward is one GEMM of
 # 2 x (2N) flops per pixel (4 flops per interaction), the adjoint two
@@ -78,6 +88,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=8.0,
                     help="target wall seconds of each oracle sample (forward, adjoint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="time the FP64 CPU oracle per workload (serial and all cores)")
+    ap.add_argument("--only", action="store_true",
+                    help="time --variant alone (no other variants, no precision study)")
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "small", "mesh8k", "mesh64k", "adjoint", "fit4k"],
                     help="paper: the headline fwd+adjoint step; the others print one report "
@@ -131,6 +145,18 @@ for _v in ALL_VARIANTS[2:]:
     FWD_KERNEL[_v], ADJ_KERNEL[_v] = 5, 6
 
 
+def _launch_stats(prefix, each):
+    """Mean (the roofline's figure), median and min of per-launch kernel times."""
+    import statistics
+
+    if not each:
+        return {prefix + "_kernel_ms": float("nan"), prefix + "_kernel_median_ms": float("nan"),
+                prefix + "_kernel_min_ms": float("nan")}
+    return {prefix + "_kernel_ms": sum(each) / len(each),
+            prefix + "_kernel_median_ms": statistics.median(each),
+            prefix + "_kernel_min_ms": min(each)}
+
+
 def timed_steps(step, steps, torch):
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -158,6 +184,9 @@ def main():
         return
     if args.sweep:
         report_sweep(args)
+        return
+    if args.oracle_timing:
+        report_oracle_timing(args)
         return
     if args.workload != "paper":
         report_workload(args)
@@ -191,7 +220,7 @@ def main():
         return step
 
     results = {}
-    others = [v for v in ALL_VARIANTS if v != args.variant]
+    others = [] if args.only else [v for v in ALL_VARIANTS if v != args.variant]
     for variant in [args.variant] + others:
         step = make_step(variant)
         for _ in range(args.warmup):
@@ -202,13 +231,11 @@ def main():
         B.profile_enable(True)
         ms, wall = timed_steps(step, args.steps, torch)
         B.profile_enable(False)
-        fk = FWD_KERNEL[variant]
-        ak = ADJ_KERNEL[variant]
-        nf, tf = B.profile_read(fk)
-        na, ta_ = B.profile_read(ak)
-        results[variant] = dict(ms_per_step=ms, wall_s=wall, fwd_kernel_ms=tf / max(nf, 1),
-                                adj_kernel_ms=ta_ / max(na, 1), fwd_launches=nf,
-                                adj_launches=na)
+        fe = B.profile_read_each(FWD_KERNEL[variant])
+        ae = B.profile_read_each(ADJ_KERNEL[variant])
+        results[variant] = dict(ms_per_step=ms, wall_s=wall, fwd_launches=len(fe),
+                                adj_launches=len(ae), **_launch_stats("fwd", fe),
+                                **_launch_stats("adj", ae))
 
     # Accuracy of every forward variant against the FP64 GPU forward, and of
     # every adjoint against the compensated one (relative L2 per gradient
@@ -219,7 +246,7 @@ def main():
     G64 = (I64 - T.double()).float()
     ref = [t.double() for t in B.backward(x, y, z, a, G64, nx, ny, wl.pitch, wl.wavelength,
                                          "compensated")]
-    for variant in ALL_VARIANTS:
+    for variant in results:
         Iv = B.forward(x, y, z, a, nx, ny, wl.pitch, wl.wavelength, variant)
         errs[variant] = float((Iv.double() - I64).abs().max().item()) / suma
         gv = B.backward(x, y, z, a, G64, nx, ny, wl.pitch, wl.wavelength, variant)
@@ -241,9 +268,16 @@ def main():
             "ms_per_step": r["ms_per_step"],
             "gpps": inter / (r["ms_per_step"] * 1e-3) / 1e9,
             "fwd_kernel_ms": r["fwd_kernel_ms"],
+            "fwd_kernel_median_ms": r["fwd_kernel_median_ms"],
+            "fwd_kernel_min_ms": r["fwd_kernel_min_ms"],
             "adj_kernel_ms": r["adj_kernel_ms"],
+            "adj_kernel_median_ms": r["adj_kernel_median_ms"],
+            "adj_kernel_min_ms": r["adj_kernel_min_ms"],
             "fwd_gpps": inter / (r["fwd_kernel_ms"] * 1e-3) / 1e9,
             "adj_gpps": inter / (r["adj_kernel_ms"] * 1e-3) / 1e9,
+            # N nx ny / (t_fwd + t_adj): the two main kernels alone
+            "combined_kernel_gpps": inter / ((r["fwd_kernel_ms"] + r["adj_kernel_ms"]) * 1e-3)
+                                    / 1e9,
             "fwd_roofline_frac": (inter / (r["fwd_kernel_ms"] * 1e-3)) /
                                  peak_interactions("fwd_" + variant),
             "adj_roofline_frac": (inter / (r["adj_kernel_ms"] * 1e-3)) /
@@ -286,6 +320,8 @@ def main():
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                             "copy-calibrated)",
             "slots_per_interaction": SLOTS.get(adj_key),
+            "frac_if_packed": (achieved * 1e9 / (PEAK_SLOTS / SLOTS_PACKED[adj_key])
+                               if adj_key in SLOTS_PACKED else None),
             "flops_per_interaction": (MFMA_FLOPS[args.variant][1]
                                       if args.variant in MFMA_FLOPS else None),
             "peak_slots_per_s": PEAK_SLOTS,
@@ -376,6 +412,101 @@ def cpu_baseline(cloud, target, nx, ny, wl, seconds, x, y, z, a, T, variant, B, 
             "grad_rel_l2": rel,
         },
     }
+
+
+def report_oracle_timing(args):
+    """The FP64 CPU oracle timed on this host, per workload (part of the
+    cpu_baseline leg: the only code here that calls the oracle), beside the
+    compensated GPU kernels on the same workload.  Serial (one thread): the
+    256x256 N=64 and 1920x1024 N=1024 full grids.  All allowed cores: the
+    1920x1024 full grid, the 1920x1080 mesh clouds and the 3840x2160 N=16384
+    cloud on 8192 seeded pixels plus the corners and the centre, and the
+    1024x1024 N=4096 cloud's full forward and full adjoint."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1002_0916_amd import binding as B
+    from paper_1002_0916_amd import workloads as W
+
+    B.load_library()
+    dev = torch.device("cuda:0")
+    cores = len(os.sched_getaffinity(0))
+    rows = []
+
+    def gpu_rates(cloud, nx, ny, wl, G=None):
+        x, y, z, a = (torch.from_numpy(v).to(dev) for v in cloud.astuple())
+        inter = cloud.n * nx * ny
+        fms = _kernel_ms(B, torch, lambda: B.forward(x, y, z, a, nx, ny, wl.pitch,
+                                                     wl.wavelength, "compensated"),
+                         B.KERNEL_FWD_COMPENSATED, 5)
+        out = {"gpu_fwd_gpps": inter / (fms * 1e-3) / 1e9}
+        if G is not None:
+            g = torch.from_numpy(np.ascontiguousarray(G, dtype=np.float32)).to(dev)
+            ams = _kernel_ms(B, torch, lambda: B.backward(x, y, z, a, g, nx, ny, wl.pitch,
+                                                          wl.wavelength, "compensated"),
+                             B.KERNEL_ADJ_COMPENSATED, 5)
+            out["gpu_adj_gpps"] = inter / (ams * 1e-3) / 1e9
+        return out
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    def add(name, what, threads, inter, secs, gpu_gpps):
+        rate = inter / secs
+        rows.append({"workload": name, "what": what, "threads": threads,
+                     "interactions": inter, "seconds": secs, "oracle_gpps": rate / 1e9,
+                     "gpu_gpps": gpu_gpps, "gpu_over_oracle": gpu_gpps * 1e9 / rate})
+        print("  %-10s %-34s %2d thr %9.3e int %8.2f s %8.4f G/s" %
+              (name, what, threads, inter, secs, rate / 1e9), file=sys.stderr, flush=True)
+
+    def full_fwd(name, cloud, wl, threads, gpu):
+        t = timed(lambda: oracle.forward(*cloud.astuple(), wl.nx, wl.ny, wl.pitch,
+                                         wl.wavelength, threads=threads))
+        add(name, "forward, full grid", threads, cloud.n * wl.nx * wl.ny, t,
+            gpu["gpu_fwd_gpps"])
+
+    def subset_fwd(name, cloud, wl, seed, gpu):
+        px, py = W.sample_pixels(seed, wl.nx, wl.ny, 8192)
+        t = timed(lambda: oracle.forward_at(*cloud.astuple(), wl.nx, wl.ny, px, py, wl.pitch,
+                                            wl.wavelength, threads=cores))
+        add(name, "forward, %d sampled pixels" % px.shape[0], cores, cloud.n * px.shape[0], t,
+            gpu["gpu_fwd_gpps"])
+
+    wl0, wl1 = W.WORKLOADS["small"], W.WORKLOADS["paper"]
+    c0, c1 = W.small_cloud(), W.paper_cloud()
+    g0, g1 = gpu_rates(c0, wl0.nx, wl0.ny, wl0), gpu_rates(c1, wl1.nx, wl1.ny, wl1)
+    full_fwd("small", c0, wl0, 1, g0)
+    full_fwd("paper", c1, wl1, 1, g1)
+    full_fwd("paper", c1, wl1, cores, g1)
+    wl2a, wl2b = W.WORKLOADS["mesh8k"], W.WORKLOADS["mesh64k"]
+    c2a, c2b = W.mesh_clouds()
+    subset_fwd("mesh8k", c2a, wl2a, 81, gpu_rates(c2a, wl2a.nx, wl2a.ny, wl2a))
+    subset_fwd("mesh64k", c2b, wl2b, 82, gpu_rates(c2b, wl2b.nx, wl2b.ny, wl2b))
+    wl4 = W.WORKLOADS["fit4k"]
+    _, c4 = W.fit_clouds()
+    subset_fwd("fit4k", c4, wl4, 84, gpu_rates(c4, wl4.nx, wl4.ny, wl4))
+    # 1024x1024 N=4096: full forward and full adjoint, G = I - T with I the
+    # oracle hologram of the trainable cloud and T that of the hidden one.
+    wl3 = W.WORKLOADS["adjoint"]
+    h3, c3 = W.adjoint_clouds()
+    t0 = time.perf_counter()
+    I3 = oracle.forward(*c3.astuple(), wl3.nx, wl3.ny, wl3.pitch, wl3.wavelength, threads=cores)
+    tf = time.perf_counter() - t0
+    T3 = oracle.forward(*h3.astuple(), wl3.nx, wl3.ny, wl3.pitch, wl3.wavelength, threads=cores)
+    G3 = (I3 - T3).astype(np.float32).astype(np.float64)
+    g3 = gpu_rates(c3, wl3.nx, wl3.ny, wl3, G3)
+    inter3 = c3.n * wl3.nx * wl3.ny
+    add("adjoint", "forward, full grid", cores, inter3, tf, g3["gpu_fwd_gpps"])
+    ta = timed(lambda: oracle.adjoint(*c3.astuple(), wl3.nx, wl3.ny, G3, pitch=wl3.pitch,
+                                      wavelength=wl3.wavelength, threads=cores))
+    add("adjoint", "adjoint, all points, full grid", cores, inter3, ta, g3["gpu_adj_gpps"])
+    print(json.dumps({"mode": "oracle_timing", "cores": cores, "cpu_model": _cpu_model(),
+                      "oracle": "FP64, libm cos/sin, row-parallel (bitwise equal to serial)",
+                      "gpu": "compensated kernels, mean of 5 launches after 1 warm-up",
+                      "rows": rows}), flush=True)
 
 
 def _kernel_ms(B, torch, fn, kernel, reps):

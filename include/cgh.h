@@ -172,6 +172,16 @@ int cgh_version(void);
 int cgh_profile_enable(int32_t on);
 int cgh_profile_read(int32_t kernel, int64_t* launches, double* total_ms);
 
+/*
+ * As cgh_profile_read, and also copies the first `capacity` per-launch
+ * durations (milliseconds, in launch order) into the host array `each_ms`
+ * (caller-owned, may be NULL when capacity is 0).  *launches counts all
+ * recorded launches, also those beyond `capacity`.  CGH_EINVAL for a negative
+ * capacity or a NULL array with capacity > 0.
+ */
+int cgh_profile_read_each(int32_t kernel, int64_t* launches, double* total_ms, float* each_ms,
+                          int64_t capacity);
+
 #ifdef __cplusplus
 }
 #endif

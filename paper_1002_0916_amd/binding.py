@@ -40,7 +40,8 @@ VARIANTS = {"plain": PLAIN, "fast": PLAIN, "compensated": COMPENSATED, "comp": C
             "separable_f16": SEPARABLE_F16, "separable_bf16": SEPARABLE_BF16}
 
 EXPORTED = ("cgh_workspace_bytes", "cgh_forward", "cgh_forward_f64", "cgh_backward",
-            "cgh_strerror", "cgh_version", "cgh_profile_enable", "cgh_profile_read")
+            "cgh_strerror", "cgh_version", "cgh_profile_enable", "cgh_profile_read",
+            "cgh_profile_read_each")
 
 _lib = None
 _lock = threading.Lock()
@@ -82,6 +83,9 @@ def load_library():
         lib.cgh_profile_enable.restype = ctypes.c_int
         lib.cgh_profile_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(f64)]
         lib.cgh_profile_read.restype = ctypes.c_int
+        lib.cgh_profile_read_each.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(f64),
+                                              ctypes.POINTER(ctypes.c_float), i64]
+        lib.cgh_profile_read_each.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -241,3 +245,14 @@ def profile_read(kernel: int):
     _check(load_library().cgh_profile_read(int(kernel), ctypes.byref(launches),
                                            ctypes.byref(total)))
     return int(launches.value), float(total.value)
+
+
+def profile_read_each(kernel: int, capacity: int = 4096):
+    """Per-launch durations (ms, launch order) recorded for ``kernel`` since
+    the last read (at most ``capacity`` of them)."""
+    launches = ctypes.c_int64(0)
+    total = ctypes.c_double(0.0)
+    buf = (ctypes.c_float * max(capacity, 1))()
+    _check(load_library().cgh_profile_read_each(int(kernel), ctypes.byref(launches),
+                                                ctypes.byref(total), buf, int(capacity)))
+    return [float(buf[i]) for i in range(min(int(launches.value), capacity))]

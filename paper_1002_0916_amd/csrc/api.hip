@@ -253,8 +253,8 @@ inline int hip_status(hipError_t e) { return e == hipSuccess ? CGH_OK : CGH_EHIP
 
 // I = P Q^T with P = (A cY, -A sY) [nyp][k2], Q = (cX, sX) [nxp][k2].
 int forward_separable(const Plan& p, const Workspace& w, float* hologram, hipStream_t s) {
-  hipError_t e = launch_sep_table(w.xrec, nullptr, p.npad, p.nx, p.nxp, w.sep_x, s);
-  if (e == hipSuccess) e = launch_sep_table(w.yrec, w.amp, p.npad, p.ny, p.nyp, w.sep_y, s);
+  hipError_t e =
+      launch_sep_tables(w.xrec, w.yrec, w.amp, p.npad, p.nx, p.nxp, p.ny, p.nyp, w.sep_x, w.sep_y, s);
   if (e != hipSuccess) return CGH_EHIP;
   const EventPair ev = profile_begin(CGH_KERNEL_FWD_SEPARABLE, s);
   if (p.sep_splits == 1) {
@@ -279,8 +279,8 @@ int backward_separable(const Plan& p, const Workspace& w, const float* x, const 
                        const float* z, const float* a, double pitch, double wavelength,
                        const float* g, float* gx, float* gy, float* gz, float* ga,
                        hipStream_t s) {
-  hipError_t e = launch_sep_table(w.xrec, nullptr, p.npad, p.nx, p.nxp, w.sep_x, s);
-  if (e == hipSuccess) e = launch_sep_table(w.yrec, nullptr, p.npad, p.ny, p.nyp, w.sep_y, s);
+  hipError_t e = launch_sep_tables(w.xrec, w.yrec, nullptr, p.npad, p.nx, p.nxp, p.ny, p.nyp,
+                                   w.sep_x, w.sep_y, s);
   if (e == hipSuccess) e = launch_sep_pad(g, p.nx, p.ny, p.nyp, p.nxp, w.sep_g, s);
   if (e != hipSuccess) return CGH_EHIP;
   const int64_t u_plane = p.k2 * p.nxp, p_plane = p.k2 * p.nyp;
@@ -303,13 +303,8 @@ int backward_separable(const Plan& p, const Workspace& w, const float* x, const 
 // (A_j, resp. G, divided by a power of two recorded in w.hmax).
 int forward_separable_half(const Plan& p, const Workspace& w, float* hologram, hipStream_t s) {
   const int hm = half_mode(p.variant);
-  hipError_t e = launch_absmax(w.amp, p.npad, w.hmax, s);
-  if (e == hipSuccess)
-    e = launch_sep_table_half(hm, w.xrec, nullptr, nullptr, p.npad, p.nx, p.nxp, false, w.hx_hi,
-                              w.hx_lo, s);
-  if (e == hipSuccess)
-    e = launch_sep_table_half(hm, w.yrec, w.amp, w.hmax, p.npad, p.ny, p.nyp, false, w.hy_hi,
-                              w.hy_lo, s);
+  hipError_t e = launch_absmax(w.amp, p.npad, w.hmax, s);  // w.hmax cleared by prep
+  if (e == hipSuccess) e = launch_sep_tables_half(hm, p, w, s);
   if (e != hipSuccess) return CGH_EHIP;
   const EventPair ev = profile_begin(CGH_KERNEL_FWD_SEPARABLE, s);
   if (p.sep_splits == 1) {
@@ -333,16 +328,8 @@ int backward_separable_half(const Plan& p, const Workspace& w, const float* x, c
                             const float* g, float* gx, float* gy, float* gz, float* ga,
                             hipStream_t s) {
   const int hm = half_mode(p.variant);
-  hipError_t e = launch_absmax(g, (int64_t)p.nx * p.ny, w.hmax, s);
-  if (e == hipSuccess)
-    e = launch_sep_table_half(hm, w.xrec, nullptr, nullptr, p.npad, p.nx, p.nxp, true, w.hx_hi,
-                              w.hx_lo, s);
-  if (e == hipSuccess)
-    e = launch_sep_table_half(hm, w.yrec, nullptr, nullptr, p.npad, p.ny, p.nyp, true, w.hy_hi,
-                              w.hy_lo, s);
-  if (e == hipSuccess)
-    e = launch_sep_pad_half(hm, g, p.nx, p.ny, p.nyp, p.nxp, w.hmax, w.hg_hi, w.hg_lo, w.hgt_hi,
-                            w.hgt_lo, s);
+  hipError_t e = launch_absmax(g, (int64_t)p.nx * p.ny, w.hmax, s);  // w.hmax cleared by prep
+  if (e == hipSuccess) e = launch_sep_adj_operands_half(hm, p, w, g, s);
   if (e != hipSuccess) return CGH_EHIP;
   const int64_t u_plane = p.k2 * p.nxp, p_plane = p.k2 * p.nyp;
   const EventPair ev = profile_begin(CGH_KERNEL_ADJ_SEPARABLE, s);
@@ -493,8 +480,10 @@ int cgh_profile_enable(int32_t on) {
   return CGH_OK;
 }
 
-int cgh_profile_read(int32_t kernel, int64_t* launches, double* total_ms) {
+int cgh_profile_read_each(int32_t kernel, int64_t* launches, double* total_ms, float* each_ms,
+                          int64_t capacity) {
   if (kernel < 0 || kernel >= CGH_KERNEL_COUNT || !launches || !total_ms) return CGH_EINVAL;
+  if (capacity < 0 || (capacity > 0 && !each_ms)) return CGH_EINVAL;
   Profiler& P = profiler();
   std::vector<EventPair> mine;
   {
@@ -511,6 +500,7 @@ int cgh_profile_read(int32_t kernel, int64_t* launches, double* total_ms) {
       rc = CGH_EHIP;
       continue;
     }
+    if (count < capacity) each_ms[count] = ms;
     sum += ms;
     ++count;
   }
@@ -521,6 +511,10 @@ int cgh_profile_read(int32_t kernel, int64_t* launches, double* total_ms) {
   *launches = count;
   *total_ms = sum;
   return rc;
+}
+
+int cgh_profile_read(int32_t kernel, int64_t* launches, double* total_ms) {
+  return cgh_profile_read_each(kernel, launches, total_ms, nullptr, 0);
 }
 
 }  // extern "C"

@@ -148,6 +148,8 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op);
 Workspace carve(const Plan& p, void* base);
 
 // Launch wrappers (return the hipError_t of the launch).
+// The prep kernel also clears w.hmax (when the plan has one) for the
+// abs-max reduction that follows it on the stream.
 hipError_t launch_prep(const float* x, const float* y, const float* z, const float* a, int64_t n,
                        int64_t npad, double pitch, double wavelength, const Workspace& w,
                        bool want64, hipStream_t s);
@@ -166,8 +168,14 @@ hipError_t launch_gemm_f32(bool a_kcontig, bool b_kcontig, const float* A, int64
                            int64_t slice_stride, int M, int N, int K, int splits, int m_valid,
                            int n_valid, hipStream_t s);
 // Separable variant (separable.hip).
-hipError_t launch_sep_table(const float* rec, const float* amp, int64_t npad, int rows_valid,
-                            int rows_pad, float* tab, hipStream_t s);
+// Grid of the per-axis table kernels: x over points (256 per workgroup), y a
+// few workgroup rows that stride over the table rows.
+dim3 table_grid(int64_t npad, int rows);
+// Both axis tables (x: (cX, sX) [nxp][k2]; y: (A cY, -A sY) with amp, else
+// (cY, sY), [nyp][k2]) in one launch.
+hipError_t launch_sep_tables(const float* xrec, const float* yrec, const float* amp, int64_t npad,
+                             int nx, int nxp, int ny, int nyp, float* tab_x, float* tab_y,
+                             hipStream_t s);
 hipError_t launch_sep_sum_slices(const float* C, int splits, int64_t slice_stride, int64_t ldc,
                                  int nx, int ny, float* out, hipStream_t s);
 hipError_t launch_sep_pad(const float* g, int nx, int ny, int rows_pad, int cols_pad, float* gp,
@@ -199,15 +207,16 @@ __device__ __forceinline__ float pow2_scale(unsigned max_bits) {
   return ldexpf(1.0f, e);
 }
 
-// Separable variants with half-precision contractions (separable.hip).
+// Separable variants with half-precision contractions (separable_half.hip).
+// launch_absmax raises *out (cleared beforehand, by the prep kernel) to the
+// float bits of max |v|.
 hipError_t launch_absmax(const float* v, int64_t count, unsigned* out, hipStream_t s);
-hipError_t launch_sep_table_half(int mode, const float* rec, const float* amp,
-                                 const unsigned* amp_max, int64_t npad, int rows_valid,
-                                 int rows_pad, bool transposed, uint16_t* hi, uint16_t* lo,
-                                 hipStream_t s);
-hipError_t launch_sep_pad_half(int mode, const float* g, int nx, int ny, int nyp, int nxp,
-                               const unsigned* g_max, uint16_t* gh, uint16_t* gl, uint16_t* gth,
-                               uint16_t* gtl, hipStream_t s);
+// Forward operands: X [nxp][k2] and Y [nyp][k2] (with A_j / 2^e) planes.
+hipError_t launch_sep_tables_half(int mode, const Plan& p, const Workspace& w, hipStream_t s);
+// Adjoint operands: Xt [k2][nxp], Yt [k2][nyp], and G / 2^e as G [nyp][nxp]
+// and Gt [nxp][nyp] planes, in one launch.
+hipError_t launch_sep_adj_operands_half(int mode, const Plan& p, const Workspace& w,
+                                        const float* g, hipStream_t s);
 // Runs per point group for this launch (<= p.regions), from the occupancy of
 // the adjoint kernel on the current device.
 int adj_runs(const Plan& p);

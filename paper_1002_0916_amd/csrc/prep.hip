@@ -20,8 +20,10 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ x,
                                                    float* __restrict__ amp,
                                                    float* __restrict__ xrec,
                                                    float* __restrict__ yrec,
-                                                   double4* __restrict__ rec64) {
+                                                   double4* __restrict__ rec64,
+                                                   unsigned* __restrict__ clear) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (clear && j == 0) *clear = 0u;
   if (j >= npad) return;
   // Padding points have zero amplitude at a valid position, so they add
   // exactly 0 to every sum.
@@ -95,7 +97,7 @@ hipError_t launch_prep(const float* x, const float* y, const float* z, const flo
                        bool want64, hipStream_t s) {
   hipLaunchKernelGGL(prep_kernel, dim3(blocks_for(npad, 256)), dim3(256), 0, s, x, y, z, a, n,
                      npad, pitch, wavelength, w.plain, w.amp, w.xrec, w.yrec,
-                     want64 ? w.rec64 : (double4*)nullptr);
+                     want64 ? w.rec64 : (double4*)nullptr, w.hmax);
   return hipGetLastError();
 }
 

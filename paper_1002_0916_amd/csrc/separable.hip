@@ -27,30 +27,38 @@ namespace cgh {
 
 namespace {
 
-// tab[h][2j], tab[h][2j+1] = (s0 cos 2 pi phi, s1 sin 2 pi phi), phi the axis
-// phase of point j at coordinate h; (s0, s1) = (1, 1), or (A_j, -A_j) when
-// amp is given.  Rows h >= rows_valid are zero.
-__global__ __launch_bounds__(256) void sep_table_kernel(const float* __restrict__ rec,
-                                                        const float* __restrict__ amp,
-                                                        int64_t npad, int rows_valid,
-                                                        int64_t total, float2* __restrict__ tab) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  const int64_t j = t % npad;
-  const int h = (int)(t / npad);
-  float2 v = make_float2(0.0f, 0.0f);
-  if (h < rows_valid) {
-    const float* r = rec + j * kAxisRec;
-    const float phi = axis_phase((float)h, r[0], r[1], r[2], r[3], r[4]);
-    const float c = cos_rev(phi), s = sin_rev(phi);
-    if (amp) {
-      const float A = amp[j];
-      v = make_float2(A * c, -(A * s));
-    } else {
-      v = make_float2(c, s);
-    }
+// Both axis tables in one launch: tab[h][2j], tab[h][2j+1] = (s0 cos 2 pi
+// phi, s1 sin 2 pi phi), phi the axis phase of point j at coordinate h;
+// (s0, s1) = (1, 1), or (A_j, -A_j) for the y table when amp is given.
+// Table rows r in [0, nxp) are the x table [nxp][npad] (float2 entries),
+// rows [nxp, nxp + nyp) the y table [nyp][npad]; rows h >= nx (resp. ny) are
+// zero.  Lane -> point j = blockIdx.x * 256 + threadIdx.x; the workgroups of
+// one x index stride over the rows.
+__global__ __launch_bounds__(256) void sep_table_kernel(
+    const float* __restrict__ xrec, const float* __restrict__ yrec,
+    const float* __restrict__ amp, int64_t npad, int nx, int nxp, int ny, int nyp,
+    float2* __restrict__ tab_x, float2* __restrict__ tab_y) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= npad) return;
+  float xr[5], yr[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    xr[i] = xrec[j * kAxisRec + i];
+    yr[i] = yrec[j * kAxisRec + i];
   }
-  tab[t] = v;
+  const float A = amp ? amp[j] : 1.0f;
+  for (int r = blockIdx.y; r < nxp + nyp; r += gridDim.y) {
+    const bool is_x = r < nxp;
+    const int h = is_x ? r : r - nxp;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (h < (is_x ? nx : ny)) {
+      const float* q = is_x ? xr : yr;
+      const float phi = axis_phase((float)h, q[0], q[1], q[2], q[3], q[4]);
+      const float c = cos_rev(phi), s = sin_rev(phi);
+      v = (!is_x && amp) ? make_float2(A * c, -(A * s)) : make_float2(c, s);
+    }
+    (is_x ? tab_x : tab_y)[(int64_t)h * npad + j] = v;
+  }
 }
 
 // I[y][x] = sum over split slices of C[s][y][x] (fixed order).
@@ -170,11 +178,21 @@ inline unsigned blocks_for(int64_t count, int threads) {
 
 }  // namespace
 
-hipError_t launch_sep_table(const float* rec, const float* amp, int64_t npad, int rows_valid,
-                            int rows_pad, float* tab, hipStream_t s) {
-  const int64_t total = (int64_t)rows_pad * npad;
-  hipLaunchKernelGGL(sep_table_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, rec, amp,
-                     npad, rows_valid, total, (float2*)tab);
+dim3 table_grid(int64_t npad, int rows) {
+  // About 1024 workgroups: enough to fill the chip, few enough that each
+  // thread reuses its point's records over many rows.
+  const unsigned bx = blocks_for(npad, 256);
+  unsigned gy = bx >= 1024 ? 1 : 1024 / bx;
+  if (gy > (unsigned)rows) gy = (unsigned)rows;
+  return dim3(bx, gy);
+}
+
+hipError_t launch_sep_tables(const float* xrec, const float* yrec, const float* amp, int64_t npad,
+                             int nx, int nxp, int ny, int nyp, float* tab_x, float* tab_y,
+                             hipStream_t s) {
+  const dim3 grid = table_grid(npad, nxp + nyp);
+  hipLaunchKernelGGL(sep_table_kernel, grid, dim3(256), 0, s, xrec, yrec, amp, npad, nx, nxp, ny,
+                     nyp, (float2*)tab_x, (float2*)tab_y);
   return hipGetLastError();
 }
 

@@ -173,6 +173,15 @@ def test_profile_read_rejects_bad_kernel(lib):
     assert lib.cgh_profile_read(-1, ctypes.byref(n), ctypes.byref(t)) == B.CGH_EINVAL
     assert lib.cgh_profile_read(7, ctypes.byref(n), ctypes.byref(t)) == B.CGH_EINVAL
     assert lib.cgh_profile_read(0, None, ctypes.byref(t)) == B.CGH_EINVAL
+    buf = (ctypes.c_float * 4)()
+    each = lib.cgh_profile_read_each
+    assert each(7, ctypes.byref(n), ctypes.byref(t), buf, 4) == B.CGH_EINVAL
+    assert each(0, ctypes.byref(n), ctypes.byref(t), buf, -1) == B.CGH_EINVAL
+    assert each(0, ctypes.byref(n), ctypes.byref(t), None, 4) == B.CGH_EINVAL
+    # nothing recorded (timing is off): zero launches, nothing written
+    buf[0] = -1.0
+    assert each(0, ctypes.byref(n), ctypes.byref(t), buf, 4) == B.CGH_OK
+    assert n.value == 0 and t.value == 0.0 and buf[0] == -1.0
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

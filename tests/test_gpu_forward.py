@@ -195,6 +195,16 @@ def test_kernel_profiling_counts_launches():
     n, ms = B.profile_read(B.KERNEL_FWD_COMPENSATED)
     assert n == 3 and ms > 0
     assert B.profile_read(B.KERNEL_FWD_COMPENSATED) == (0, 0.0)
+    # per-launch durations: one per launch, summing to the total
+    B.profile_enable(True)
+    try:
+        for _ in range(4):
+            B.forward(x, y, z, a, 256, 256, variant="separable_f16x3")
+    finally:
+        B.profile_enable(False)
+    each = B.profile_read_each(B.KERNEL_FWD_SEPARABLE)
+    assert len(each) == 4 and all(v > 0 for v in each)
+    assert B.profile_read(B.KERNEL_FWD_SEPARABLE) == (0, 0.0)
 
 
 def test_separable_symmetry_to_rounding():
