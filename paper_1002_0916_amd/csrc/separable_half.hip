@@ -7,8 +7,8 @@
 //   kHalfF16    v ~ fp16(v)
 //   kHalfBF16   v ~ bf16(v)
 //   kHalfF16x3  v ~ hi + lo, hi = fp16(v), lo = fp16(v - hi); the GEMM forms
-//               hi*hi + hi*lo + lo*hi, dropping only lo*lo (about 2^-24
-//               relative), so the products keep FP32-level accuracy.
+//               hi*hi + hi*lo + lo*hi, dropping only lo*lo (at most 2^-22 of
+//               the product), so the products keep near-FP32 accuracy.
 //
 // fp16 has a narrow exponent range, so operands whose scale is not fixed
 // (the amplitudes A_j in the forward, the upstream gradient G in the adjoint)
