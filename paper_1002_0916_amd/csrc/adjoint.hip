@@ -13,10 +13,8 @@
 // wave-uniform and reaches the lanes through scalar loads, one strip row
 // (kAdjCols floats) at a time.  The pixel-dependent factors separate by axis,
 // r^2 = dx^2 + dy^2, so per strip the lane keeps the column phases (or dx) and
-// the column sums of G sin(theta) in registers, and per row it takes the row
-// phase (or forms dy^2) once and folds the row sum of G sin(theta) with dy and
-// dy^2.  The compensated column and row phases come from the point-major
-// tables of the phase-table kernel (coalesced loads: lane = point).
+// the column sums of G sin(theta) in registers, and per row it forms the row
+// phase (or dy^2) once and folds the row sum of G sin(theta) with dy and dy^2.
 // Per interaction that leaves the phase, sin and cos, and three fused
 // multiply-adds with G taken straight from an SGPR.
 //
@@ -37,8 +35,8 @@ namespace {
 
 template <int VARIANT>
 __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
-    const float4* __restrict__ plain, const float* __restrict__ xtab,
-    const float* __restrict__ rowtab, const float* __restrict__ g, int64_t ldg, int ny,
+    const float4* __restrict__ plain, const float* __restrict__ xrec,
+    const float* __restrict__ yrec, const float* __restrict__ g, int64_t ldg, int ny,
     int64_t strip_rows, int npad, float4* __restrict__ partial) {
   // Neighbouring runs and all point groups of a run share G: keep them on
   // one XCD.
@@ -51,34 +49,40 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
 
   const float4 pr = plain[j];
   const float px = pr.x, py = pr.y, prev = pr.z;
+  float xc = 0.f, xph = 0.f, xpl = 0.f, xb = 0.f, xd = 0.f;
+  float yc = 0.f, yph = 0.f, ypl = 0.f, yb = 0.f, yd = 0.f;
+  if (VARIANT == 1) {
+    const float* rx = xrec + (int64_t)j * kAxisRec;
+    xc = rx[0]; xph = rx[1]; xpl = rx[2]; xb = rx[3]; xd = rx[4];
+    const float* ry = yrec + (int64_t)j * kAxisRec;
+    yc = ry[0]; yph = ry[1]; ypl = ry[2]; yb = ry[3]; yd = ry[4];
+  }
 
   float Sc0 = 0.f, Sc1 = 0.f, Sx = 0.f, Sy = 0.f, Sr = 0.f;
   float CX[kAdjCols], SgC[kAdjCols];
   int col0 = 0, row1 = 0;
 
   // G of one strip row lives in SGPRs.  Rows are software-pipelined with two
-  // ping-pong buffers: the scalar loads of the next row (and, compensated,
-  // the vector load of its row phase) are issued right after the first use
-  // of the current row (which waits for it), so the rest of the row's
-  // arithmetic covers their latency.  The last row of a segment re-reads
-  // itself, so every load stays in bounds.
-  auto load_row = [&](int row, float* dst, float& ry) {
+  // ping-pong buffers: the scalar loads of the next row are issued right
+  // after the first use of the current row (which waits for it), so the rest
+  // of the row's arithmetic covers their latency.  The last row of a segment
+  // re-reads itself, so every load stays in bounds.
+  auto load_row = [&](int row, float* dst) {
     const float* src = g + (int64_t)row * ldg + col0;
 #pragma unroll
     for (int k = 0; k < kAdjCols; ++k) dst[k] = src[k];
-    if (VARIANT == 1) ry = rowtab[(int64_t)row * npad + j];
   };
-  auto do_row = [&](int row, const float* gc, float ryc, float* gn, float& ryn) {
+  auto do_row = [&](int row, const float* gc, float* gn) {
     const float yh = (float)row;
     const float dy = yh - py;
     const float dy2 = dy * dy;
-    const float RY = VARIANT == 1 ? ryc : dy2;
+    const float RY = VARIANT == 1 ? axis_phase(yh, yc, yph, ypl, yb, yd) : dy2;
     float sr0 = 0.f, sr1 = 0.f;
 #pragma unroll
     for (int c = 0; c < kAdjCols; ++c) {
       if (c == 1) {
         __builtin_amdgcn_sched_barrier(0);
-        load_row(min(row + 1, row1 - 1), gn, ryn);
+        load_row(min(row + 1, row1 - 1), gn);
         __builtin_amdgcn_sched_barrier(0);
       }
       const float G = gc[c];
@@ -113,18 +117,18 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     // Column terms: the compensated x-phase of each strip column, or dx.
 #pragma unroll
     for (int c = 0; c < kAdjCols; ++c) {
-      CX[c] = VARIANT == 1 ? xtab[(int64_t)(col0 + c) * npad + j] : (float)(col0 + c) - px;
+      const float h = (float)(col0 + c);
+      CX[c] = VARIANT == 1 ? axis_phase(h, xc, xph, xpl, xb, xd) : h - px;
       SgC[c] = 0.f;
     }
     float gA[kAdjCols], gB[kAdjCols];
-    float ryA = 0.f, ryB = 0.f;
-    load_row(row0, gA, ryA);
+    load_row(row0, gA);
     int row = row0;
     for (; row + 1 < row1; row += 2) {
-      do_row(row, gA, ryA, gB, ryB);
-      do_row(row + 1, gB, ryB, gA, ryA);
+      do_row(row, gA, gB);
+      do_row(row + 1, gB, gA);
     }
-    if (row < row1) do_row(row, gA, ryA, gB, ryB);
+    if (row < row1) do_row(row, gA, gB);
 #pragma unroll
     for (int c = 0; c < kAdjCols; ++c) {
       const float dx = (float)(col0 + c) - px;
@@ -244,12 +248,12 @@ hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* g,
   const dim3 grid(runs, p.ngroups);
   if (p.variant == 1) {
     hipLaunchKernelGGL(adj_partial_kernel<1>, grid, dim3(kAdjThreads), 0, s,
-                       (const float4*)w.plain, (const float*)w.xtab, (const float*)w.rowtab, g,
-                       ldg, p.ny, p.strip_rows, (int)p.npad, (float4*)w.partial);
+                       (const float4*)w.plain, (const float*)w.xrec, (const float*)w.yrec, g, ldg,
+                       p.ny, p.strip_rows, (int)p.npad, (float4*)w.partial);
   } else {
     hipLaunchKernelGGL(adj_partial_kernel<0>, grid, dim3(kAdjThreads), 0, s,
-                       (const float4*)w.plain, (const float*)nullptr, (const float*)nullptr, g,
-                       ldg, p.ny, p.strip_rows, (int)p.npad, (float4*)w.partial);
+                       (const float4*)w.plain, (const float*)w.xrec, (const float*)w.yrec, g, ldg,
+                       p.ny, p.strip_rows, (int)p.npad, (float4*)w.partial);
   }
   return hipGetLastError();
 }

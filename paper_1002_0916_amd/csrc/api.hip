@@ -96,12 +96,6 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   p.off_ytab = (op == CGH_OP_FORWARD && variant == CGH_COMPENSATED)
                    ? take((size_t)p.groups * np * kCompRows * sizeof(float))
                    : 0;
-  if (variant == CGH_COMPENSATED && op == CGH_OP_FORWARD)
-    p.off_xtab = take((size_t)p.fwd_gx * kWave * np * sizeof(float));
-  if (variant == CGH_COMPENSATED && op == CGH_OP_BACKWARD) {
-    p.off_xtab = take((size_t)p.nsx * kAdjCols * np * sizeof(float));
-    p.off_rowtab = take((size_t)ny * np * sizeof(float));
-  }
   const bool direct_adj = op == CGH_OP_BACKWARD && !is_separable(variant);
   p.off_partial = direct_adj ? take((size_t)p.regions * np * sizeof(float4)) : 0;
   p.off_gpad = (direct_adj && p.need_gpad)
@@ -143,10 +137,6 @@ Workspace carve(const Plan& p, void* base) {
   w.rec64 = p.op == CGH_OP_FORWARD_F64 ? (double4*)(b + p.off_rec64) : nullptr;
   w.ytab = (p.op == CGH_OP_FORWARD && p.variant == CGH_COMPENSATED) ? (float*)(b + p.off_ytab)
                                                                      : nullptr;
-  const bool comp_tables =
-      p.variant == CGH_COMPENSATED && (p.op == CGH_OP_FORWARD || p.op == CGH_OP_BACKWARD);
-  w.xtab = comp_tables ? (float*)(b + p.off_xtab) : nullptr;
-  w.rowtab = (comp_tables && p.op == CGH_OP_BACKWARD) ? (float*)(b + p.off_rowtab) : nullptr;
   const bool direct_adj = p.op == CGH_OP_BACKWARD && !is_separable(p.variant);
   w.partial = direct_adj ? (float*)(b + p.off_partial) : nullptr;
   w.gpad = (direct_adj && p.need_gpad) ? (float*)(b + p.off_gpad) : nullptr;
@@ -386,11 +376,13 @@ int cgh_forward(const float* x, const float* y, const float* z, const float* a, 
   rc = check_workspace(p, workspace, workspace_bytes);
   if (rc) return rc;
   const Workspace w = carve(p, workspace);
-  hipError_t e = launch_prep(p, x, y, z, a, pitch, wavelength, w, false, s);
+  hipError_t e = launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, false, s);
   if (e != hipSuccess) return CGH_EHIP;
   if (variant == CGH_SEPARABLE) return forward_separable(p, w, hologram, s);
   if (half_mode(variant) >= 0) return forward_separable_half(p, w, hologram, s);
   if (variant == CGH_COMPENSATED) {
+    e = launch_ytab(p, w, s);
+    if (e != hipSuccess) return CGH_EHIP;
     const EventPair ev = profile_begin(CGH_KERNEL_FWD_COMPENSATED, s);
     e = launch_fwd_comp(p, w, hologram, s);
     profile_end(CGH_KERNEL_FWD_COMPENSATED, ev, s);
@@ -414,7 +406,7 @@ int cgh_forward_f64(const float* x, const float* y, const float* z, const float*
   rc = check_workspace(p, workspace, workspace_bytes);
   if (rc) return rc;
   const Workspace w = carve(p, workspace);
-  hipError_t e = launch_prep(p, x, y, z, a, pitch, wavelength, w, true, s);
+  hipError_t e = launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, true, s);
   if (e != hipSuccess) return CGH_EHIP;
   const EventPair ev = profile_begin(CGH_KERNEL_FWD_F64, s);
   e = launch_fwd_f64(p, w, hologram, s);
@@ -437,7 +429,7 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
   rc = check_workspace(p, workspace, workspace_bytes);
   if (rc) return rc;
   const Workspace w = carve(p, workspace);
-  hipError_t e = launch_prep(p, x, y, z, a, pitch, wavelength, w, false, s);
+  hipError_t e = launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, false, s);
   if (e != hipSuccess) return CGH_EHIP;
   if (variant == CGH_SEPARABLE)
     return backward_separable(p, w, x, y, z, a, pitch, wavelength, grad_hologram, grad_x, grad_y,

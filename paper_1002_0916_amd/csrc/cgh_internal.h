@@ -108,9 +108,6 @@ struct Workspace {
   float* yrec;     // [npad][8]
   double4* rec64;  // [npad]
   float* ytab;     // forward, compensated: [groups][npad][kCompRows]
-  float* xtab;     // compensated: X_j(x) as [cols][npad] (cols: forward fwd_gx * 64,
-                   // adjoint nsx * kAdjCols)
-  float* rowtab;   // adjoint, compensated: Y_j(y) as [ny][npad]
   float* partial;  // adjoint: [regions][npad][4]
   float* gpad;     // adjoint: G copied to a [ny][nsx*kAdjCols] zero-padded grid
   // separable variant (tables of k2 = 2 * npad floats per row / column)
@@ -144,23 +141,21 @@ struct Plan {
   int64_t k2;
   size_t off_sep_x, off_sep_y, off_sep_c, off_sep_g, off_sep_u, off_sep_p;
   size_t off_hx, off_hy, off_hg, off_hgt, off_hmax;  // half variants (hi plane; lo follows)
-  size_t off_plain, off_amp, off_xrec, off_yrec, off_rec64, off_ytab, off_xtab, off_rowtab;
-  size_t off_partial, off_gpad, total;
+  size_t off_plain, off_amp, off_xrec, off_yrec, off_rec64, off_ytab, off_partial, off_gpad, total;
 };
 
 Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op);
 Workspace carve(const Plan& p, void* base);
 
 // Launch wrappers (return the hipError_t of the launch).
-// Point records (and rec64 when want64), plus, for the compensated
-// variants, the axis-phase tables in the same launch (forward: ytab and
-// xtab; adjoint: xtab and rowtab).  Also clears w.hmax (when the plan has
-// one) for the abs-max reduction that follows it on the stream.
-hipError_t launch_prep(const Plan& p, const float* x, const float* y, const float* z,
-                       const float* a, double pitch, double wavelength, const Workspace& w,
+// The prep kernel also clears w.hmax (when the plan has one) for the
+// abs-max reduction that follows it on the stream.
+hipError_t launch_prep(const float* x, const float* y, const float* z, const float* a, int64_t n,
+                       int64_t npad, double pitch, double wavelength, const Workspace& w,
                        bool want64, hipStream_t s);
 hipError_t launch_fill_zero_f32(float* p, int64_t count, hipStream_t s);
 hipError_t launch_fill_zero_f64(double* p, int64_t count, hipStream_t s);
+hipError_t launch_ytab(const Plan& p, const Workspace& w, hipStream_t s);
 hipError_t launch_fwd_plain(const Plan& p, const Workspace& w, float* out, hipStream_t s);
 hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s);
 hipError_t launch_fwd_f64(const Plan& p, const Workspace& w, double* out, hipStream_t s);

@@ -58,17 +58,16 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_plain_kernel(const float4* __
 // Compensated FP32: the phase separates exactly as X_j(x_h) + Y_j(y_h) with
 // X_j(x_h) = Prev (x_h - x_j)^2 and Y_j(y_h) = Prev (y_h - y_j)^2.  Each part
 // is formed on the integer pixel grid as a compensated split product reduced
-// mod 1 (axis_phase), once per (point, row) and (point, column) by the
-// phase-table kernel.  Y comes from the per-row table (wave-uniform, scalar
-// loads).  X depends on the column and the point only, and the waves of a
-// workgroup share their 64 columns, so the workgroup stages X for a tile of
-// kTile points in LDS, double buffered so that filling tile t+1 overlaps
-// consuming tile t.  For the fill, lane l holds point l of the tile and wave
-// w copies its share of the columns from the column-major X table (one
-// coalesced 256-byte load per column, issued a tile ahead).  Per
-// interaction: one LDS-fed add, the native cosine (no fract: the sum stays
-// within a few revolutions) and one fma.
-__global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(const float* __restrict__ xtab,
+// mod 1 (axis_phase).  Y comes from the per-row table (wave-uniform, scalar
+// loads).  X depends on the column and the point only, and the four waves of
+// a workgroup share their 64 columns, so the workgroup computes X once per
+// tile of kTile points into LDS, double buffered so that filling tile t+1
+// overlaps consuming tile t.  For the fill, lane l holds point l of the tile
+// (its record arrives by one coalesced vector load, issued a tile ahead) and
+// wave w computes the 16 columns 16w..16w+15.  Per interaction: one LDS-fed
+// add, the native cosine (no fract: the sum stays within a few revolutions)
+// and one fma.
+__global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(const float* __restrict__ xrec,
                                                                const float* __restrict__ amp,
                                                                const float* __restrict__ ytab,
                                                                int npad, int nx, int ny,
@@ -87,16 +86,18 @@ __global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(const float* __r
   const int ntiles = npad / kTile;
   constexpr int kColsPerWave = kWave / kCompWaves;
 
-  // This wave's columns of the X table for point tile * kTile + lane.
-  const float* __restrict__ xsrc = xtab + (int64_t)(col0 + wave * kColsPerWave) * npad + lane;
-  auto load_x = [&](int tile, float* v) {
-#pragma unroll
-    for (int k = 0; k < kColsPerWave; ++k) v[k] = xsrc[(int64_t)k * npad + tile * kTile];
+  // This lane's point record {c, Ph, Pl, b, d} for the tile being filled.
+  auto load_rec = [&](int tile, float4& r0, float& r1) {
+    const float* r = xrec + (int64_t)(tile * kTile + lane) * kAxisRec;
+    r0 = *reinterpret_cast<const float4*>(r);
+    r1 = r[4];
   };
-  auto fill = [&](int buf, const float* v) {
+  auto fill = [&](int buf, const float4& r0, float r1) {
 #pragma unroll
-    for (int k = 0; k < kColsPerWave; ++k)
-      xs[buf][lane * kTilePitch + wave * kColsPerWave + k] = v[k];
+    for (int k = 0; k < kColsPerWave; ++k) {
+      const int c = wave * kColsPerWave + k;
+      xs[buf][lane * kTilePitch + c] = axis_phase((float)(col0 + c), r0.x, r0.y, r0.z, r0.w, r1);
+    }
   };
   // Row phases and amplitudes of kCompUnroll consecutive points, read
   // through scalar loads (SGPRs) and software-pipelined one group ahead: the
@@ -134,16 +135,17 @@ __global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(const float* __r
     }
   };
   float yA[kCompUnroll * kCompRows], aA[kCompUnroll], yB[kCompUnroll * kCompRows], aB[kCompUnroll];
-  float xv[kColsPerWave];
-  load_x(0, xv);
-  fill(0, xv);
-  if (ntiles > 1) load_x(1, xv);
+  float4 r0;
+  float r1;
+  load_rec(0, r0, r1);
+  fill(0, r0, r1);
+  if (ntiles > 1) load_rec(1, r0, r1);
   load_group(0, yA, aA);
   __syncthreads();
   for (int t = 0; t < ntiles; ++t) {
     if (t + 1 < ntiles) {
-      fill((t + 1) & 1, xv);
-      if (t + 2 < ntiles) load_x(t + 2, xv);
+      fill((t + 1) & 1, r0, r1);
+      if (t + 2 < ntiles) load_rec(t + 2, r0, r1);
     }
     const float* xt = xs[t & 1];
     for (int p = 0; p < kTile; p += 2 * kCompUnroll) {
@@ -191,7 +193,7 @@ hipError_t launch_fwd_plain(const Plan& p, const Workspace& w, float* out, hipSt
 
 hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s) {
   hipLaunchKernelGGL(fwd_comp_kernel, dim3(p.fwd_gx, p.comp_gy), dim3(kCompThreads), 0, s,
-                     (const float*)w.xtab, (const float*)w.amp, (const float*)w.ytab, (int)p.npad,
+                     (const float*)w.xrec, (const float*)w.amp, (const float*)w.ytab, (int)p.npad,
                      p.nx, p.ny, out);
   return hipGetLastError();
 }
