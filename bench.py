@@ -157,6 +157,28 @@ def _launch_stats(prefix, each):
             prefix + "_kernel_min_ms": min(each)}
 
 
+def graph_step_ms(step, steps, torch):
+    """The same step captured once into a HIP graph (torch.cuda.graph) and
+    replayed ``steps`` times: ms per replay, or None if capture fails."""
+    try:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        graph.replay()
+        ms, _ = timed_steps(graph.replay, steps, torch)
+        del graph
+        return ms
+    except RuntimeError as e:
+        print("graph capture failed: %s" % e, file=sys.stderr)
+        return None
+
+
 def timed_steps(step, steps, torch):
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -236,6 +258,7 @@ def main():
         results[variant] = dict(ms_per_step=ms, wall_s=wall, fwd_launches=len(fe),
                                 adj_launches=len(ae), **_launch_stats("fwd", fe),
                                 **_launch_stats("adj", ae))
+        results[variant]["graph_ms_per_step"] = graph_step_ms(step, args.steps, torch)
 
     # Accuracy of every forward variant against the FP64 GPU forward, and of
     # every adjoint against the compensated one (relative L2 per gradient
@@ -264,9 +287,13 @@ def main():
 
     def kernel_summary(variant):
         r = results[variant]
+        g = r.get("graph_ms_per_step")
         return {
             "ms_per_step": r["ms_per_step"],
             "gpps": inter / (r["ms_per_step"] * 1e-3) / 1e9,
+            # the same step replayed from one captured HIP graph
+            "graph_ms_per_step": g,
+            "graph_gpps": inter / (g * 1e-3) / 1e9 if g else None,
             "fwd_kernel_ms": r["fwd_kernel_ms"],
             "fwd_kernel_median_ms": r["fwd_kernel_median_ms"],
             "fwd_kernel_min_ms": r["fwd_kernel_min_ms"],
