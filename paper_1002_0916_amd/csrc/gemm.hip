@@ -41,15 +41,25 @@ template <bool KCONTIG>
 __device__ __forceinline__ Frag16 load_tile(const float* __restrict__ src, int64_t ld, int row0,
                                             int k0) {
   const int t = threadIdx.x;
-  // K-contiguous: thread t takes row t / 2 and the k half t % 2 (16 consecutive
-  // k); M/N-contiguous: k = t % 32 and 16 consecutive rows from (t / 32) * 16.
-  const float* p = KCONTIG ? src + (int64_t)(row0 + t / 2) * ld + k0 + (t & 1) * 16
-                           : src + (int64_t)(k0 + (t & 31)) * ld + row0 + (t >> 5) * 16;
   Frag16 r;
-  r.q0 = *reinterpret_cast<const float4*>(p + 0);
-  r.q1 = *reinterpret_cast<const float4*>(p + 4);
-  r.q2 = *reinterpret_cast<const float4*>(p + 8);
-  r.q3 = *reinterpret_cast<const float4*>(p + 12);
+  if (KCONTIG) {
+    // 16-byte chunks c = t + 256 i (i = 0..3) of the tile's 1024, chunk c
+    // holding k = 4 (c % 8) .. 4 (c % 8) + 3 of row c / 8: each wave
+    // instruction reads 8 whole 128-byte row segments.
+    const float* p = src + (int64_t)(row0 + t / 8) * ld + k0 + (t & 7) * 4;
+    r.q0 = *reinterpret_cast<const float4*>(p);
+    r.q1 = *reinterpret_cast<const float4*>(p + 32 * ld);
+    r.q2 = *reinterpret_cast<const float4*>(p + 64 * ld);
+    r.q3 = *reinterpret_cast<const float4*>(p + 96 * ld);
+  } else {
+    // M/N-contiguous: k = t % 32 and 16 consecutive rows from (t / 32) * 16
+    // (k fastest across lanes keeps the transposing LDS stores conflict-free).
+    const float* p = src + (int64_t)(k0 + (t & 31)) * ld + row0 + (t >> 5) * 16;
+    r.q0 = *reinterpret_cast<const float4*>(p + 0);
+    r.q1 = *reinterpret_cast<const float4*>(p + 4);
+    r.q2 = *reinterpret_cast<const float4*>(p + 8);
+    r.q3 = *reinterpret_cast<const float4*>(p + 12);
+  }
   return r;
 }
 
@@ -64,11 +74,11 @@ template <bool KCONTIG>
 __device__ __forceinline__ void store_tile(float* __restrict__ lds, const Frag16& r) {
   const int t = threadIdx.x;
   if (KCONTIG) {
-    float* p = lds + (t / 2) * kPitch + (t & 1) * 16;
-    *reinterpret_cast<float4*>(p + 0) = r.q0;
-    *reinterpret_cast<float4*>(p + 4) = r.q1;
-    *reinterpret_cast<float4*>(p + 8) = r.q2;
-    *reinterpret_cast<float4*>(p + 12) = r.q3;
+    float* p = lds + (t / 8) * kPitch + (t & 7) * 4;
+    *reinterpret_cast<float4*>(p) = r.q0;
+    *reinterpret_cast<float4*>(p + 32 * kPitch) = r.q1;
+    *reinterpret_cast<float4*>(p + 64 * kPitch) = r.q2;
+    *reinterpret_cast<float4*>(p + 96 * kPitch) = r.q3;
   } else {
     const int k = t & 31, m0 = (t >> 5) * 16;
     store_col(lds, m0 + 0, k, r.q0);

@@ -34,26 +34,29 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kHBM = 128, kHBN = 128, kHBK = 32, kHPitch = kHBK + 8;
 constexpr int kHThreads = 256;
 
-// 16 consecutive k of one row: this thread's share of a 128 x 32 plane tile.
+// This thread's share of a 128 x 32 plane tile: 16-byte chunks c = t and
+// t + 256 of the tile's 512, chunk c holding k = 8 (c % 4) .. 8 (c % 4) + 7 of
+// row c / 4.  Each wave instruction thus reads 16 whole 64-byte row
+// segments.
 struct Half16 {
-  uint4 lo8, hi8;  // elements k0..k0+7, k0+8..k0+15
+  uint4 lo8, hi8;  // chunks t and t + 256
 };
 
 __device__ __forceinline__ Half16 load_plane(const uint16_t* __restrict__ src, int64_t ld, int row0,
                                              int k0) {
   const int t = threadIdx.x;
-  const uint16_t* p = src + (int64_t)(row0 + t / 2) * ld + k0 + (t & 1) * 16;
+  const uint16_t* p = src + (int64_t)(row0 + t / 4) * ld + k0 + (t & 3) * 8;
   Half16 r;
   r.lo8 = *reinterpret_cast<const uint4*>(p);
-  r.hi8 = *reinterpret_cast<const uint4*>(p + 8);
+  r.hi8 = *reinterpret_cast<const uint4*>(p + 64 * ld);
   return r;
 }
 
 __device__ __forceinline__ void store_plane(uint16_t* __restrict__ lds, const Half16& r) {
   const int t = threadIdx.x;
-  uint16_t* p = lds + (t / 2) * kHPitch + (t & 1) * 16;
+  uint16_t* p = lds + (t / 4) * kHPitch + (t & 3) * 8;
   *reinterpret_cast<uint4*>(p) = r.lo8;
-  *reinterpret_cast<uint4*>(p + 8) = r.hi8;
+  *reinterpret_cast<uint4*>(p + 64 * kHPitch) = r.hi8;
 }
 
 template <int MODE>
