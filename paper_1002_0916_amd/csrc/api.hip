@@ -113,8 +113,10 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   p.off_sep_c = (sep && fwd && p.sep_splits > 1)
                     ? take((size_t)p.sep_splits * nyp * nxp * sizeof(float))
                     : 0;
-  p.off_sep_u = (sep && bwd) ? take((size_t)p.sep_splits_u * k2 * nxp * sizeof(float)) : 0;
-  p.off_sep_p = (sep && bwd) ? take((size_t)p.sep_splits_p * k2 * nyp * sizeof(float)) : 0;
+  p.off_fold_x =
+      (sep && bwd) ? take((size_t)p.sep_splits_u * (nxp / 128) * np * sizeof(float4)) : 0;
+  p.off_fold_y =
+      (sep && bwd) ? take((size_t)p.sep_splits_p * (nyp / 128) * np * sizeof(float4)) : 0;
   // 16-bit planes: hi, then (f16x3) lo at the next 256-byte boundary.
   const size_t planes = hm == kHalfF16x3 ? 2 : 1;
   auto take_planes = [&](size_t elems) { return take(planes * align256(elems * 2)); };
@@ -148,8 +150,8 @@ Workspace carve(const Plan& p, void* base) {
   w.sep_y = f32 ? (float*)(b + p.off_sep_y) : nullptr;
   w.sep_g = (f32 && bwd) ? (float*)(b + p.off_sep_g) : nullptr;
   w.sep_c = (sep && fwd && p.sep_splits > 1) ? (float*)(b + p.off_sep_c) : nullptr;
-  w.sep_u = (sep && bwd) ? (float*)(b + p.off_sep_u) : nullptr;
-  w.sep_p = (sep && bwd) ? (float*)(b + p.off_sep_p) : nullptr;
+  w.fold_x = (sep && bwd) ? (float4*)(b + p.off_fold_x) : nullptr;
+  w.fold_y = (sep && bwd) ? (float4*)(b + p.off_fold_y) : nullptr;
   if (hm >= 0) {
     const size_t k2 = (size_t)p.k2, nxp = (size_t)p.nxp, nyp = (size_t)p.nyp;
     const bool split = hm == kHalfF16x3;
@@ -259,11 +261,11 @@ int forward_separable(const Plan& p, const Workspace& w, float* hologram, hipStr
   const EventPair ev = profile_begin(CGH_KERNEL_FWD_SEPARABLE, s);
   if (p.sep_splits == 1) {
     e = launch_gemm_f32(true, true, w.sep_y, p.k2, w.sep_x, p.k2, hologram, p.nx, 0, p.nyp,
-                        p.nxp, (int)p.k2, 1, p.ny, p.nx, s);
+                        p.nxp, (int)p.k2, 1, p.ny, p.nx, nullptr, s);
   } else {
     const int64_t plane = (int64_t)p.nyp * p.nxp;
     e = launch_gemm_f32(true, true, w.sep_y, p.k2, w.sep_x, p.k2, w.sep_c, p.nxp, plane, p.nyp,
-                        p.nxp, (int)p.k2, p.sep_splits, p.nyp, p.nxp, s);
+                        p.nxp, (int)p.k2, p.sep_splits, p.nyp, p.nxp, nullptr, s);
   }
   profile_end(CGH_KERNEL_FWD_SEPARABLE, ev, s);
   if (e != hipSuccess) return CGH_EHIP;
@@ -274,28 +276,28 @@ int forward_separable(const Plan& p, const Workspace& w, float* hologram, hipStr
 }
 
 // U = Y^T G (Y = (cY, sY) [nyp][k2]), Pm = X^T G^T (X = (cX, sX) [nxp][k2]),
-// then the per-point fold.
-int backward_separable(const Plan& p, const Workspace& w, const float* x, const float* y,
-                       const float* z, const float* a, double pitch, double wavelength,
-                       const float* g, float* gx, float* gy, float* gz, float* ga,
-                       hipStream_t s) {
+// each folded per point in its GEMM epilogue, then the per-point sums.
+int backward_separable(const Plan& p, const Workspace& w, const float* z, const float* a,
+                       double pitch, double wavelength, const float* g, float* gx, float* gy,
+                       float* gz, float* ga, hipStream_t s) {
   hipError_t e = launch_sep_tables(w.xrec, w.yrec, nullptr, p.npad, p.nx, p.nxp, p.ny, p.nyp,
                                    w.sep_x, w.sep_y, s);
   if (e == hipSuccess) e = launch_sep_pad(g, p.nx, p.ny, p.nyp, p.nxp, w.sep_g, s);
   if (e != hipSuccess) return CGH_EHIP;
-  const int64_t u_plane = p.k2 * p.nxp, p_plane = p.k2 * p.nyp;
+  const FoldSpec fx{1, w.xrec, w.plain, p.nx, w.fold_x};
+  const FoldSpec fy{2, w.yrec, w.plain, p.ny, w.fold_y};
   const EventPair ev = profile_begin(CGH_KERNEL_ADJ_SEPARABLE, s);
-  // U[k][x] = sum_y Y[y][k] G[y][x]: A = Y stored [y][k], B = G stored [y][x].
-  e = launch_gemm_f32(false, false, w.sep_y, p.k2, w.sep_g, p.nxp, w.sep_u, p.nxp, u_plane,
-                      (int)p.k2, p.nxp, p.nyp, p.sep_splits_u, (int)p.k2, p.nxp, s);
+  // U[k][x] = sum_y Y[y][k] G[y][x]: A = Y stored [y][k], B = G stored [y][x];
+  // folded in the epilogue.
+  e = launch_gemm_f32(false, false, w.sep_y, p.k2, w.sep_g, p.nxp, nullptr, 0, 0, (int)p.k2,
+                      p.nxp, p.nyp, p.sep_splits_u, (int)p.k2, p.nxp, &fx, s);
   // Pm[k][y] = sum_x X[x][k] G[y][x]: A = X stored [x][k], B = G stored [y][x].
   if (e == hipSuccess)
-    e = launch_gemm_f32(false, true, w.sep_x, p.k2, w.sep_g, p.nxp, w.sep_p, p.nyp, p_plane,
-                        (int)p.k2, p.nyp, p.nxp, p.sep_splits_p, (int)p.k2, p.nyp, s);
+    e = launch_gemm_f32(false, true, w.sep_x, p.k2, w.sep_g, p.nxp, nullptr, 0, 0, (int)p.k2,
+                        p.nyp, p.nxp, p.sep_splits_p, (int)p.k2, p.nyp, &fy, s);
   profile_end(CGH_KERNEL_ADJ_SEPARABLE, ev, s);
   if (e != hipSuccess) return CGH_EHIP;
-  e = launch_sep_fold(p, w, w.sep_u, p.sep_splits_u, u_plane, p.nxp, w.sep_p, p.sep_splits_p,
-                      p_plane, p.nyp, x, y, z, a, pitch, wavelength, gx, gy, gz, ga, s);
+  e = launch_sep_finalize(p, w, z, a, pitch, wavelength, gx, gy, gz, ga, s);
   return hip_status(e);
 }
 
@@ -309,11 +311,12 @@ int forward_separable_half(const Plan& p, const Workspace& w, float* hologram, h
   const EventPair ev = profile_begin(CGH_KERNEL_FWD_SEPARABLE, s);
   if (p.sep_splits == 1) {
     e = launch_gemm_half(hm, w.hy_hi, w.hy_lo, p.k2, w.hx_hi, w.hx_lo, p.k2, hologram, p.nx, 0,
-                         p.nyp, p.nxp, (int)p.k2, 1, p.ny, p.nx, w.hmax, s);
+                         p.nyp, p.nxp, (int)p.k2, 1, p.ny, p.nx, w.hmax, nullptr, s);
   } else {
     const int64_t plane = (int64_t)p.nyp * p.nxp;
     e = launch_gemm_half(hm, w.hy_hi, w.hy_lo, p.k2, w.hx_hi, w.hx_lo, p.k2, w.sep_c, p.nxp,
-                         plane, p.nyp, p.nxp, (int)p.k2, p.sep_splits, p.nyp, p.nxp, w.hmax, s);
+                         plane, p.nyp, p.nxp, (int)p.k2, p.sep_splits, p.nyp, p.nxp, w.hmax, nullptr,
+                         s);
   }
   profile_end(CGH_KERNEL_FWD_SEPARABLE, ev, s);
   if (e != hipSuccess) return CGH_EHIP;
@@ -323,29 +326,27 @@ int forward_separable_half(const Plan& p, const Workspace& w, float* hologram, h
   return hip_status(e);
 }
 
-int backward_separable_half(const Plan& p, const Workspace& w, const float* x, const float* y,
-                            const float* z, const float* a, double pitch, double wavelength,
-                            const float* g, float* gx, float* gy, float* gz, float* ga,
-                            hipStream_t s) {
+int backward_separable_half(const Plan& p, const Workspace& w, const float* z, const float* a,
+                            double pitch, double wavelength, const float* g, float* gx, float* gy,
+                            float* gz, float* ga, hipStream_t s) {
   const int hm = half_mode(p.variant);
   hipError_t e = launch_absmax(g, (int64_t)p.nx * p.ny, w.hmax, s);  // w.hmax cleared by prep
   if (e == hipSuccess) e = launch_sep_adj_operands_half(hm, p, w, g, s);
   if (e != hipSuccess) return CGH_EHIP;
-  const int64_t u_plane = p.k2 * p.nxp, p_plane = p.k2 * p.nyp;
+  const FoldSpec fx{1, w.xrec, w.plain, p.nx, w.fold_x};
+  const FoldSpec fy{2, w.yrec, w.plain, p.ny, w.fold_y};
   const EventPair ev = profile_begin(CGH_KERNEL_ADJ_SEPARABLE, s);
-  // U[k][x] = sum_y Yt[k][y] Gt[x][y]
-  e = launch_gemm_half(hm, w.hy_hi, w.hy_lo, p.nyp, w.hgt_hi, w.hgt_lo, p.nyp, w.sep_u, p.nxp,
-                       u_plane, (int)p.k2, p.nxp, p.nyp, p.sep_splits_u, (int)p.k2, p.nxp, w.hmax,
-                       s);
-  // Pm[k][y] = sum_x Xt[k][x] G[y][x]
+  // U[k][x] = sum_y Yt[k][y] Gt[x][y], folded in the epilogue
+  e = launch_gemm_half(hm, w.hy_hi, w.hy_lo, p.nyp, w.hgt_hi, w.hgt_lo, p.nyp, nullptr, 0, 0,
+                       (int)p.k2, p.nxp, p.nyp, p.sep_splits_u, (int)p.k2, p.nxp, w.hmax, &fx, s);
+  // Pm[k][y] = sum_x Xt[k][x] G[y][x], folded in the epilogue
   if (e == hipSuccess)
-    e = launch_gemm_half(hm, w.hx_hi, w.hx_lo, p.nxp, w.hg_hi, w.hg_lo, p.nxp, w.sep_p, p.nyp,
-                         p_plane, (int)p.k2, p.nyp, p.nxp, p.sep_splits_p, (int)p.k2, p.nyp,
-                         w.hmax, s);
+    e = launch_gemm_half(hm, w.hx_hi, w.hx_lo, p.nxp, w.hg_hi, w.hg_lo, p.nxp, nullptr, 0, 0,
+                         (int)p.k2, p.nyp, p.nxp, p.sep_splits_p, (int)p.k2, p.nyp, w.hmax, &fy,
+                         s);
   profile_end(CGH_KERNEL_ADJ_SEPARABLE, ev, s);
   if (e != hipSuccess) return CGH_EHIP;
-  e = launch_sep_fold(p, w, w.sep_u, p.sep_splits_u, u_plane, p.nxp, w.sep_p, p.sep_splits_p,
-                      p_plane, p.nyp, x, y, z, a, pitch, wavelength, gx, gy, gz, ga, s);
+  e = launch_sep_finalize(p, w, z, a, pitch, wavelength, gx, gy, gz, ga, s);
   return hip_status(e);
 }
 
@@ -432,11 +433,11 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
   hipError_t e = launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, false, s);
   if (e != hipSuccess) return CGH_EHIP;
   if (variant == CGH_SEPARABLE)
-    return backward_separable(p, w, x, y, z, a, pitch, wavelength, grad_hologram, grad_x, grad_y,
+    return backward_separable(p, w, z, a, pitch, wavelength, grad_hologram, grad_x, grad_y,
                               grad_z, grad_a, s);
   if (half_mode(variant) >= 0)
-    return backward_separable_half(p, w, x, y, z, a, pitch, wavelength, grad_hologram, grad_x,
-                                   grad_y, grad_z, grad_a, s);
+    return backward_separable_half(p, w, z, a, pitch, wavelength, grad_hologram, grad_x, grad_y,
+                                   grad_z, grad_a, s);
   const float* g = grad_hologram;
   int64_t ldg = nx;
   if (p.need_gpad) {

@@ -115,8 +115,8 @@ struct Workspace {
   float* sep_y;    // [nyp][k2]  forward: (A cY, -A sY); adjoint: (cY, sY)
   float* sep_c;    // forward split-K planes [splits][nyp][nxp]
   float* sep_g;    // adjoint: G zero-padded to [nyp][nxp]
-  float* sep_u;    // adjoint: [splits_u][k2][nxp]
-  float* sep_p;    // adjoint: [splits_p][k2][nyp]
+  float4* fold_x;  // adjoint: x-part fold planes [splits_u][nxp / 128][npad]
+  float4* fold_y;  // adjoint: y-part fold planes [splits_p][nyp / 128][npad]
   // half-precision separable variants: 16-bit planes (hi, lo) and scales
   uint16_t *hx_hi, *hx_lo;   // forward [nxp][k2]; adjoint transposed [k2][nxp]
   uint16_t *hy_hi, *hy_lo;   // forward [nyp][k2] (with A); adjoint [k2][nyp]
@@ -139,7 +139,7 @@ struct Plan {
   // separable variant
   int32_t nxp, nyp, sep_splits, sep_splits_u, sep_splits_p;
   int64_t k2;
-  size_t off_sep_x, off_sep_y, off_sep_c, off_sep_g, off_sep_u, off_sep_p;
+  size_t off_sep_x, off_sep_y, off_sep_c, off_sep_g, off_fold_x, off_fold_y;
   size_t off_hx, off_hy, off_hg, off_hgt, off_hmax;  // half variants (hi plane; lo follows)
   size_t off_plain, off_amp, off_xrec, off_yrec, off_rec64, off_ytab, off_partial, off_gpad, total;
 };
@@ -160,13 +160,24 @@ hipError_t launch_fwd_plain(const Plan& p, const Workspace& w, float* out, hipSt
 hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s);
 hipError_t launch_fwd_f64(const Plan& p, const Workspace& w, double* out, hipStream_t s);
 hipError_t launch_pad_g(const Plan& p, const float* g, float* gpad, hipStream_t s);
+// Optional epilogue of the adjoint GEMMs (fold.h): instead of storing its
+// tile, each block folds it into per-point sums, written as float4 planes
+// out[(z * (N / 128) + column tile) * (M / 2) + point] for K slice z.
+struct FoldSpec {
+  int part;             // 1: x part (U), 2: y part (Pm)
+  const float* rec;     // axis records of the folded axis (xrec or yrec)
+  const float4* plain;  // point records {x, y, Prev, A}
+  int n_valid;          // nx or ny
+  float4* out;
+};
 // FP32 matrix-core GEMM (gemm.hip): C[m][n] = sum_k A(m, k) B(n, k), split
-// over `splits` K slices written to C + z * slice_stride.  M, N multiples of
-// 128; K / splits a multiple of 32.
+// over `splits` K slices written to C + z * slice_stride (or folded, when
+// fold is given: then A and B must be M/N-contiguous, as in the adjoint).
+// M, N multiples of 128; K / splits a multiple of 32.
 hipError_t launch_gemm_f32(bool a_kcontig, bool b_kcontig, const float* A, int64_t lda,
                            const float* B, int64_t ldb, float* C, int64_t ldc,
                            int64_t slice_stride, int M, int N, int K, int splits, int m_valid,
-                           int n_valid, hipStream_t s);
+                           int n_valid, const FoldSpec* fold, hipStream_t s);
 // Separable variant (separable.hip).
 // Grid of the per-axis table kernels: x over points (256 per workgroup), y a
 // few workgroup rows that stride over the table rows.
@@ -180,11 +191,11 @@ hipError_t launch_sep_sum_slices(const float* C, int splits, int64_t slice_strid
                                  int nx, int ny, float* out, hipStream_t s);
 hipError_t launch_sep_pad(const float* g, int nx, int ny, int rows_pad, int cols_pad, float* gp,
                           hipStream_t s);
-hipError_t launch_sep_fold(const Plan& p, const Workspace& w, const float* U, int su,
-                           int64_t u_stride, int64_t ldu, const float* Pm, int sp, int64_t p_stride,
-                           int64_t ldp, const float* x, const float* y, const float* z,
-                           const float* a, double pitch, double wavelength, float* gx, float* gy,
-                           float* gz, float* ga, hipStream_t s);
+// Sums the fold planes of both adjoint GEMMs per point in a fixed order
+// (FP64) and scales them into the gradients.
+hipError_t launch_sep_finalize(const Plan& p, const Workspace& w, const float* z, const float* a,
+                               double pitch, double wavelength, float* gx, float* gy, float* gz,
+                               float* ga, hipStream_t s);
 // Half-precision matrix-core GEMM (gemm_half.hip), K-contiguous 16-bit
 // planes; formats:
 constexpr int kHalfF16 = 0;    // one fp16 plane per operand
@@ -193,7 +204,8 @@ constexpr int kHalfF16x3 = 2;  // fp16 hi + lo planes, hi*hi + hi*lo + lo*hi
 hipError_t launch_gemm_half(int mode, const uint16_t* Ah, const uint16_t* Al, int64_t lda,
                             const uint16_t* Bh, const uint16_t* Bl, int64_t ldb, float* C,
                             int64_t ldc, int64_t slice_stride, int M, int N, int K, int splits,
-                            int m_valid, int n_valid, const unsigned* scale_max, hipStream_t s);
+                            int m_valid, int n_valid, const unsigned* scale_max,
+                            const FoldSpec* fold, hipStream_t s);
 
 // Power-of-two scale 2^e >= m for the largest magnitude m, given as the bits
 // of the non-negative float m (1 when m is 0 or not finite).  Dividing an

@@ -21,6 +21,7 @@
 // operands zero-padded to those sizes; the store is masked to m < m_valid,
 // n < n_valid.
 #include "cgh_internal.h"
+#include "fold.h"
 
 namespace cgh {
 
@@ -88,11 +89,11 @@ __device__ __forceinline__ void store_tile(float* __restrict__ lds, const Frag16
   }
 }
 
-template <bool AK, bool BK>
+template <bool AK, bool BK, int FOLD>
 __global__ __launch_bounds__(kGemmThreads, 2) void gemm_f32_kernel(
     const float* __restrict__ A, int64_t lda, const float* __restrict__ B, int64_t ldb,
     float* __restrict__ C, int64_t ldc, int64_t slice_stride, int k_slice, int m_valid,
-    int n_valid) {
+    int n_valid, FoldSpec fold) {
   __shared__ float As[2][kBM * kPitch];
   __shared__ float Bs[2][kBN * kPitch];
   const int lane = threadIdx.x & 63;
@@ -154,6 +155,13 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_f32_kernel(
     __syncthreads();
   }
 
+  if (FOLD) {
+    const int64_t npts = (int64_t)gridDim.y * (kBM / 2);
+    float4* dst = fold.out + ((int64_t)blockIdx.z * gridDim.x + n0 / kBN) * npts + m0 / 2;
+    fold_tile<FOLD>(acc, m0, n0, fold.rec, fold.plain, fold.n_valid, 1.0f, dst,
+                    reinterpret_cast<float4*>(&As[0][0]));
+    return;
+  }
   float* Cz = C + (int64_t)blockIdx.z * slice_stride;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -173,21 +181,36 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_f32_kernel(
 hipError_t launch_gemm_f32(bool a_kcontig, bool b_kcontig, const float* A, int64_t lda,
                            const float* B, int64_t ldb, float* C, int64_t ldc,
                            int64_t slice_stride, int M, int N, int K, int splits, int m_valid,
-                           int n_valid, hipStream_t s) {
+                           int n_valid, const FoldSpec* fold, hipStream_t s) {
   const dim3 grid(N / kBN, M / kBM, splits);
   const int k_slice = K / splits;
+  const FoldSpec f = fold ? *fold : FoldSpec{0, nullptr, nullptr, 0, nullptr};
+  if (f.part != 0) {
+    // The adjoint contractions: A M-contiguous; B N-contiguous (U) or
+    // K-contiguous (Pm).
+    if (a_kcontig) return hipErrorInvalidValue;
+    if (f.part == 1 && !b_kcontig)
+      hipLaunchKernelGGL((gemm_f32_kernel<false, false, 1>), grid, dim3(kGemmThreads), 0, s, A,
+                         lda, B, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, f);
+    else if (f.part == 2 && b_kcontig)
+      hipLaunchKernelGGL((gemm_f32_kernel<false, true, 2>), grid, dim3(kGemmThreads), 0, s, A,
+                         lda, B, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, f);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   if (a_kcontig && b_kcontig)
-    hipLaunchKernelGGL((gemm_f32_kernel<true, true>), grid, dim3(kGemmThreads), 0, s, A, lda, B,
-                       ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid);
+    hipLaunchKernelGGL((gemm_f32_kernel<true, true, 0>), grid, dim3(kGemmThreads), 0, s, A, lda,
+                       B, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, f);
   else if (!a_kcontig && !b_kcontig)
-    hipLaunchKernelGGL((gemm_f32_kernel<false, false>), grid, dim3(kGemmThreads), 0, s, A, lda,
-                       B, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid);
+    hipLaunchKernelGGL((gemm_f32_kernel<false, false, 0>), grid, dim3(kGemmThreads), 0, s, A,
+                       lda, B, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, f);
   else if (!a_kcontig && b_kcontig)
-    hipLaunchKernelGGL((gemm_f32_kernel<false, true>), grid, dim3(kGemmThreads), 0, s, A, lda, B,
-                       ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid);
+    hipLaunchKernelGGL((gemm_f32_kernel<false, true, 0>), grid, dim3(kGemmThreads), 0, s, A, lda,
+                       B, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, f);
   else
-    hipLaunchKernelGGL((gemm_f32_kernel<true, false>), grid, dim3(kGemmThreads), 0, s, A, lda, B,
-                       ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid);
+    hipLaunchKernelGGL((gemm_f32_kernel<true, false, 0>), grid, dim3(kGemmThreads), 0, s, A, lda,
+                       B, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, f);
   return hipGetLastError();
 }
 

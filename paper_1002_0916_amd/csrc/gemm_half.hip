@@ -22,6 +22,7 @@
 #include <stdint.h>
 
 #include "cgh_internal.h"
+#include "fold.h"
 
 namespace cgh {
 
@@ -68,12 +69,12 @@ __device__ __forceinline__ floatx16 mma(uint4 a, uint4 b, floatx16 c) {
                                                 __builtin_bit_cast(halfx8, b), c, 0, 0, 0);
 }
 
-template <int MODE>
+template <int MODE, int FOLD>
 __global__ __launch_bounds__(kHThreads, 2) void gemm_half_kernel(
     const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al, int64_t lda,
     const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl, int64_t ldb,
     float* __restrict__ C, int64_t ldc, int64_t slice_stride, int k_slice, int m_valid,
-    int n_valid, const unsigned* __restrict__ scale_max) {
+    int n_valid, const unsigned* __restrict__ scale_max, FoldSpec fold) {
   constexpr bool kSplit = MODE == kHalfF16x3;
   constexpr int kPlane = kHBM * kHPitch;
   // [buffer][plane]: A hi, B hi, and (split) A lo, B lo
@@ -160,6 +161,13 @@ __global__ __launch_bounds__(kHThreads, 2) void gemm_half_kernel(
 
   // Undo the power-of-two operand scaling (exact).
   const float alpha = scale_max ? pow2_scale(*scale_max) : 1.0f;
+  if (FOLD) {
+    const int64_t npts = (int64_t)gridDim.y * (kHBM / 2);
+    float4* dst = fold.out + ((int64_t)blockIdx.z * gridDim.x + n0 / kHBN) * npts + m0 / 2;
+    fold_tile<FOLD>(acc, m0, n0, fold.rec, fold.plain, fold.n_valid, alpha, dst,
+                    reinterpret_cast<float4*>(&smem[0][0][0]));
+    return;
+  }
   float* Cz = C + (int64_t)blockIdx.z * slice_stride;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -174,24 +182,42 @@ __global__ __launch_bounds__(kHThreads, 2) void gemm_half_kernel(
     }
 }
 
+template <int MODE>
+hipError_t launch_mode(const uint16_t* Ah, const uint16_t* Al, int64_t lda, const uint16_t* Bh,
+                       const uint16_t* Bl, int64_t ldb, float* C, int64_t ldc,
+                       int64_t slice_stride, int M, int N, int K, int splits, int m_valid,
+                       int n_valid, const unsigned* scale_max, const FoldSpec* fold,
+                       hipStream_t s) {
+  const dim3 grid(N / kHBN, M / kHBM, splits);
+  const int k_slice = K / splits;
+  const FoldSpec f = fold ? *fold : FoldSpec{0, nullptr, nullptr, 0, nullptr};
+  if (f.part == 1)
+    hipLaunchKernelGGL((gemm_half_kernel<MODE, 1>), grid, dim3(kHThreads), 0, s, Ah, Al, lda, Bh,
+                       Bl, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, scale_max, f);
+  else if (f.part == 2)
+    hipLaunchKernelGGL((gemm_half_kernel<MODE, 2>), grid, dim3(kHThreads), 0, s, Ah, Al, lda, Bh,
+                       Bl, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, scale_max, f);
+  else
+    hipLaunchKernelGGL((gemm_half_kernel<MODE, 0>), grid, dim3(kHThreads), 0, s, Ah, Al, lda, Bh,
+                       Bl, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, scale_max, f);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_gemm_half(int mode, const uint16_t* Ah, const uint16_t* Al, int64_t lda,
                             const uint16_t* Bh, const uint16_t* Bl, int64_t ldb, float* C,
                             int64_t ldc, int64_t slice_stride, int M, int N, int K, int splits,
-                            int m_valid, int n_valid, const unsigned* scale_max, hipStream_t s) {
-  const dim3 grid(N / kHBN, M / kHBM, splits);
-  const int k_slice = K / splits;
+                            int m_valid, int n_valid, const unsigned* scale_max,
+                            const FoldSpec* fold, hipStream_t s) {
   if (mode == kHalfF16x3)
-    hipLaunchKernelGGL(gemm_half_kernel<kHalfF16x3>, grid, dim3(kHThreads), 0, s, Ah, Al, lda,
-                       Bh, Bl, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, scale_max);
-  else if (mode == kHalfBF16)
-    hipLaunchKernelGGL(gemm_half_kernel<kHalfBF16>, grid, dim3(kHThreads), 0, s, Ah, Al, lda,
-                       Bh, Bl, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, scale_max);
-  else
-    hipLaunchKernelGGL(gemm_half_kernel<kHalfF16>, grid, dim3(kHThreads), 0, s, Ah, Al, lda, Bh,
-                       Bl, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, scale_max);
-  return hipGetLastError();
+    return launch_mode<kHalfF16x3>(Ah, Al, lda, Bh, Bl, ldb, C, ldc, slice_stride, M, N, K,
+                                   splits, m_valid, n_valid, scale_max, fold, s);
+  if (mode == kHalfBF16)
+    return launch_mode<kHalfBF16>(Ah, Al, lda, Bh, Bl, ldb, C, ldc, slice_stride, M, N, K, splits,
+                                  m_valid, n_valid, scale_max, fold, s);
+  return launch_mode<kHalfF16>(Ah, Al, lda, Bh, Bl, ldb, C, ldc, slice_stride, M, N, K, splits,
+                               m_valid, n_valid, scale_max, fold, s);
 }
 
 }  // namespace cgh

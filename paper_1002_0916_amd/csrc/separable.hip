@@ -18,8 +18,11 @@
 //   row sums of G sin = cY Ps + sY Pc
 //
 // and Sx, Sr (x part) and Sy, Sr (y part) fold those with dx, dx^2, dy, dy^2.
+// The adjoint GEMMs apply these folds to their own output tiles (fold.h), so
+// U and Pm are never stored; a last pass adds the per-tile sums per point.
 // This changes the algorithm (no per-interaction cosine): the per-point
-// tables cost O(N (nx + ny)) transcendentals and the bulk is FP32 MFMA work.
+// tables cost O(N (nx + ny)) transcendentals and the bulk is matrix-core
+// work.
 #include "cgh_internal.h"
 #include "phase.h"
 
@@ -87,89 +90,56 @@ __global__ __launch_bounds__(256) void sep_pad_kernel(const float* __restrict__ 
   gp[t] = (x < nx && y < ny) ? g[y * nx + x] : 0.0f;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// One workgroup (4 waves) per point: waves 0-1 fold the x part (columns
-// h = 64 k + lane, k even / odd), waves 2-3 the y part (rows, likewise).  Each
-// wave adds its terms in FP64 in a fixed lane-strided order and reduces them
-// with a butterfly; the workgroup then combines the four wave sums in a fixed
-// order and scales them into the gradients.
-__global__ __launch_bounds__(256) void sep_fold_kernel(
-    const float* __restrict__ xrec, const float* __restrict__ yrec, const float* __restrict__ Uc,
-    int su, int64_t u_stride, int64_t ldu, const float* __restrict__ Pc, int sp,
-    int64_t p_stride, int64_t ldp, int64_t n, int nx, int ny, const float* __restrict__ x,
-    const float* __restrict__ y, const float* __restrict__ z, const float* __restrict__ a,
-    double pitch, double wavelength, float* __restrict__ gx, float* __restrict__ gy,
-    float* __restrict__ gz, float* __restrict__ ga) {
-  __shared__ double part[4][3];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t j = blockIdx.x;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  if (wave < 2) {
-    // x part: Sc, Sx, Sr_x
-    const float* rx = xrec + j * kAxisRec;
-    const double xj = (double)x[j];
-    const float* urow = Uc + (2 * j) * ldu;
-    for (int h = lane + 64 * wave; h < nx; h += 128) {
-      float U = 0.0f, V = 0.0f;
-      for (int s = 0; s < su; ++s) {
-        U += urow[s * u_stride + h];
-        V += urow[s * u_stride + ldu + h];
-      }
-      const float phi = axis_phase((float)h, rx[0], rx[1], rx[2], rx[3], rx[4]);
-      const double c = cos_rev(phi), sn = sin_rev(phi);
-      s0 += c * U - sn * V;
-      const double sg = sn * U + c * V;
-      const double dx = (double)h - xj;
-      s1 += dx * sg;
-      s2 += dx * dx * sg;
+// Per point j: sums its fold planes (x part: s0 -> Sc, s1 -> Sx, s2 -> Sr;
+// y part: s1 -> Sy, s2 -> Sr) in FP64 and scales them into the gradients.
+// kFinSlices threads per point (threadIdx.y) each add the planes slice,
+// slice + kFinSlices, ... in increasing order; the slice sums are then added
+// in slice order (a fixed tree: bitwise reproducible).
+__global__ __launch_bounds__(kWave* kFinSlices) void sep_finalize_kernel(
+    const float4* __restrict__ fold_x, int planes_x, const float4* __restrict__ fold_y,
+    int planes_y, int64_t npad, int64_t n, const float* __restrict__ z,
+    const float* __restrict__ a, double pitch, double wavelength, float* __restrict__ gx,
+    float* __restrict__ gy, float* __restrict__ gz, float* __restrict__ ga) {
+  __shared__ double part[kFinSlices][5][kWave];
+  const int lane = threadIdx.x, slice = threadIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * kWave + lane;
+  double Sc = 0.0, Sx = 0.0, Srx = 0.0, Sy = 0.0, Sry = 0.0;
+  if (j < npad) {
+    for (int k = slice; k < planes_x; k += kFinSlices) {
+      const float4 v = fold_x[(int64_t)k * npad + j];
+      Sc += (double)v.x;
+      Sx += (double)v.y;
+      Srx += (double)v.z;
     }
-  } else {
-    // y part: Sy, Sr_y
-    const float* ry = yrec + j * kAxisRec;
-    const double yj = (double)y[j];
-    const float* prow = Pc + (2 * j) * ldp;
-    for (int h = lane + 64 * (wave - 2); h < ny; h += 128) {
-      float Pcos = 0.0f, Psin = 0.0f;
-      for (int s = 0; s < sp; ++s) {
-        Pcos += prow[s * p_stride + h];
-        Psin += prow[s * p_stride + ldp + h];
-      }
-      const float phi = axis_phase((float)h, ry[0], ry[1], ry[2], ry[3], ry[4]);
-      const double c = cos_rev(phi), sn = sin_rev(phi);
-      const double sr = c * Psin + sn * Pcos;
-      const double dy = (double)h - yj;
-      s1 += dy * sr;
-      s2 += dy * dy * sr;
+    for (int k = slice; k < planes_y; k += kFinSlices) {
+      const float4 v = fold_y[(int64_t)k * npad + j];
+      Sy += (double)v.y;
+      Sry += (double)v.z;
     }
   }
-  s0 = wave_sum(s0);
-  s1 = wave_sum(s1);
-  s2 = wave_sum(s2);
-  if (lane == 0) {
-    part[wave][0] = s0;
-    part[wave][1] = s1;
-    part[wave][2] = s2;
-  }
+  part[slice][0][lane] = Sc;
+  part[slice][1][lane] = Sx;
+  part[slice][2][lane] = Srx;
+  part[slice][3][lane] = Sy;
+  part[slice][4][lane] = Sry;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const double Sc = part[0][0] + part[1][0];
-    const double Sx = part[0][1] + part[1][1];
-    const double Sy = part[2][1] + part[3][1];
-    const double Sr = (part[0][2] + part[1][2]) + (part[2][2] + part[3][2]);
-    const double zj = (double)z[j], aj = (double)a[j];
-    // P_j = pi p^2 / (lambda z_j), Section 1.
-    const double P = M_PI * pitch * pitch / (wavelength * zj);
-    ga[j] = (float)Sc;
-    gx[j] = (float)(2.0 * aj * P * Sx);
-    gy[j] = (float)(2.0 * aj * P * Sy);
-    gz[j] = (float)(aj * P / zj * Sr);
+  if (slice != 0 || j >= n) return;
+  Sc = Sx = Srx = Sy = Sry = 0.0;
+  for (int k = 0; k < kFinSlices; ++k) {
+    Sc += part[k][0][lane];
+    Sx += part[k][1][lane];
+    Srx += part[k][2][lane];
+    Sy += part[k][3][lane];
+    Sry += part[k][4][lane];
   }
+  const double Sr = Srx + Sry;
+  const double zj = (double)z[j], aj = (double)a[j];
+  // P_j = pi p^2 / (lambda z_j), Section 1.
+  const double P = M_PI * pitch * pitch / (wavelength * zj);
+  ga[j] = (float)Sc;
+  gx[j] = (float)(2.0 * aj * P * Sx);
+  gy[j] = (float)(2.0 * aj * P * Sy);
+  gz[j] = (float)(aj * P / zj * Sr);
 }
 
 inline unsigned blocks_for(int64_t count, int threads) {
@@ -211,15 +181,15 @@ hipError_t launch_sep_pad(const float* g, int nx, int ny, int rows_pad, int cols
   return hipGetLastError();
 }
 
-hipError_t launch_sep_fold(const Plan& p, const Workspace& w, const float* U, int su,
-                           int64_t u_stride, int64_t ldu, const float* Pm, int sp, int64_t p_stride,
-                           int64_t ldp, const float* x, const float* y, const float* z,
-                           const float* a, double pitch, double wavelength, float* gx, float* gy,
-                           float* gz, float* ga, hipStream_t s) {
-  hipLaunchKernelGGL(sep_fold_kernel, dim3((unsigned)p.n), dim3(256), 0, s,
-                     (const float*)w.xrec, (const float*)w.yrec, U, su, u_stride, ldu, Pm, sp,
-                     p_stride, ldp, p.n, p.nx, p.ny, x, y, z, a, pitch, wavelength, gx, gy, gz,
-                     ga);
+hipError_t launch_sep_finalize(const Plan& p, const Workspace& w, const float* z, const float* a,
+                               double pitch, double wavelength, float* gx, float* gy, float* gz,
+                               float* ga, hipStream_t s) {
+  const int planes_x = p.sep_splits_u * (p.nxp / 128);
+  const int planes_y = p.sep_splits_p * (p.nyp / 128);
+  hipLaunchKernelGGL(sep_finalize_kernel, dim3(blocks_for(p.n, kWave)), dim3(kWave, kFinSlices),
+                     0, s,
+                     (const float4*)w.fold_x, planes_x, (const float4*)w.fold_y, planes_y, p.npad,
+                     p.n, z, a, pitch, wavelength, gx, gy, gz, ga);
   return hipGetLastError();
 }
 
