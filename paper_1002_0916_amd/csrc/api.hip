@@ -22,13 +22,28 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Split-K count for a GEMM of `tiles` 128 x 128 output tiles and contraction
-// length k (a multiple of 128): double it while the grid stays within one
-// round of resident GEMM workgroups (two per CU on 256 CUs), each slice keeps
-// >= 256 of k, and slices stay multiples of 32.
+// length k (a multiple of 32).  A slice holds ceil(k / 32 / splits) stages of
+// 32 (the last slice fewer, never none) and at least 8 stages.  The count
+// minimises a simple time model in units of one workgroup stage: rounds of
+// 512 resident GEMM workgroups (two per CU on 256 CUs) times the stages per
+// slice, plus the partial planes (each tile of each slice costs about six
+// stages of traffic, spread over the 512 slots).
 inline int gemm_splits(int64_t tiles, int64_t k) {
-  int s = 1;
-  while (tiles * s * 2 <= 512 && (k / 32) % (s * 2) == 0 && k / (s * 2) >= 256) s *= 2;
-  return s;
+  const int64_t chunks = k / 32;
+  int best = 1;
+  double best_time = 0.0;
+  for (int s = 1; s <= 512; ++s) {
+    const int64_t per = (chunks + s - 1) / s;
+    if (s > 1 && per < 8) break;
+    if ((chunks + per - 1) / per != s) continue;  // some slice would be empty
+    const int64_t rounds = (tiles * s + 511) / 512;
+    const double time = (double)(rounds * per) + 6.0 * (double)(s * tiles) / 512.0;
+    if (s == 1 || time < best_time) {
+      best_time = time;
+      best = s;
+    }
+  }
+  return best;
 }
 
 inline bool valid_variant(int32_t v) { return v >= CGH_PLAIN && v <= CGH_SEPARABLE_BF16; }

@@ -172,8 +172,9 @@ struct FoldSpec {
 };
 // FP32 matrix-core GEMM (gemm.hip): C[m][n] = sum_k A(m, k) B(n, k), split
 // over `splits` K slices written to C + z * slice_stride (or folded, when
-// fold is given: then A and B must be M/N-contiguous, as in the adjoint).
-// M, N multiples of 128; K / splits a multiple of 32.
+// fold is given: then A must be M-contiguous, as in the adjoint).  M, N
+// multiples of 128; K a multiple of 32; slices of ceil(K / 32 / splits)
+// chunks of 32, the last one shorter and never empty (else an error).
 hipError_t launch_gemm_f32(bool a_kcontig, bool b_kcontig, const float* A, int64_t lda,
                            const float* B, int64_t ldb, float* C, int64_t ldc,
                            int64_t slice_stride, int M, int N, int K, int splits, int m_valid,

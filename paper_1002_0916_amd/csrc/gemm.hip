@@ -92,7 +92,7 @@ __device__ __forceinline__ void store_tile(float* __restrict__ lds, const Frag16
 template <bool AK, bool BK, int FOLD>
 __global__ __launch_bounds__(kGemmThreads, 2) void gemm_f32_kernel(
     const float* __restrict__ A, int64_t lda, const float* __restrict__ B, int64_t ldb,
-    float* __restrict__ C, int64_t ldc, int64_t slice_stride, int k_slice, int m_valid,
+    float* __restrict__ C, int64_t ldc, int64_t slice_stride, int k_slice, int k_total, int m_valid,
     int n_valid, FoldSpec fold) {
   __shared__ float As[2][kBM * kPitch];
   __shared__ float Bs[2][kBN * kPitch];
@@ -103,7 +103,8 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_f32_kernel(
   const int m0 = (int)(tile / gridDim.x) * kBM;
   const int n0 = (int)(tile % gridDim.x) * kBN;
   const int kbeg = blockIdx.z * k_slice;
-  const int nstages = k_slice / kBK;
+  // the last slice may be shorter (never empty: checked at launch)
+  const int nstages = (min(kbeg + k_slice, k_total) - kbeg) / kBK;
 
   floatx16 acc[2][2];
 #pragma unroll
@@ -183,7 +184,11 @@ hipError_t launch_gemm_f32(bool a_kcontig, bool b_kcontig, const float* A, int64
                            int64_t slice_stride, int M, int N, int K, int splits, int m_valid,
                            int n_valid, const FoldSpec* fold, hipStream_t s) {
   const dim3 grid(N / kBN, M / kBM, splits);
-  const int k_slice = K / splits;
+  // Slices of k_slice (a multiple of the stage depth), the last one shorter
+  // but never empty.
+  if (splits < 1 || K < kBK || K % kBK != 0) return hipErrorInvalidValue;
+  const int k_slice = (K / kBK + splits - 1) / splits * kBK;
+  if ((int64_t)(splits - 1) * k_slice >= K) return hipErrorInvalidValue;
   const FoldSpec f = fold ? *fold : FoldSpec{0, nullptr, nullptr, 0, nullptr};
   if (f.part != 0) {
     // The adjoint contractions: A M-contiguous; B N-contiguous (U) or
@@ -191,26 +196,26 @@ hipError_t launch_gemm_f32(bool a_kcontig, bool b_kcontig, const float* A, int64
     if (a_kcontig) return hipErrorInvalidValue;
     if (f.part == 1 && !b_kcontig)
       hipLaunchKernelGGL((gemm_f32_kernel<false, false, 1>), grid, dim3(kGemmThreads), 0, s, A,
-                         lda, B, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, f);
+                         lda, B, ldb, C, ldc, slice_stride, k_slice, K, m_valid, n_valid, f);
     else if (f.part == 2 && b_kcontig)
       hipLaunchKernelGGL((gemm_f32_kernel<false, true, 2>), grid, dim3(kGemmThreads), 0, s, A,
-                         lda, B, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, f);
+                         lda, B, ldb, C, ldc, slice_stride, k_slice, K, m_valid, n_valid, f);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
   if (a_kcontig && b_kcontig)
     hipLaunchKernelGGL((gemm_f32_kernel<true, true, 0>), grid, dim3(kGemmThreads), 0, s, A, lda,
-                       B, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, f);
+                       B, ldb, C, ldc, slice_stride, k_slice, K, m_valid, n_valid, f);
   else if (!a_kcontig && !b_kcontig)
     hipLaunchKernelGGL((gemm_f32_kernel<false, false, 0>), grid, dim3(kGemmThreads), 0, s, A,
-                       lda, B, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, f);
+                       lda, B, ldb, C, ldc, slice_stride, k_slice, K, m_valid, n_valid, f);
   else if (!a_kcontig && b_kcontig)
     hipLaunchKernelGGL((gemm_f32_kernel<false, true, 0>), grid, dim3(kGemmThreads), 0, s, A, lda,
-                       B, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, f);
+                       B, ldb, C, ldc, slice_stride, k_slice, K, m_valid, n_valid, f);
   else
     hipLaunchKernelGGL((gemm_f32_kernel<true, false, 0>), grid, dim3(kGemmThreads), 0, s, A, lda,
-                       B, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, f);
+                       B, ldb, C, ldc, slice_stride, k_slice, K, m_valid, n_valid, f);
   return hipGetLastError();
 }
 

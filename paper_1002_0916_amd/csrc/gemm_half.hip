@@ -73,7 +73,7 @@ template <int MODE, int FOLD>
 __global__ __launch_bounds__(kHThreads, 2) void gemm_half_kernel(
     const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al, int64_t lda,
     const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl, int64_t ldb,
-    float* __restrict__ C, int64_t ldc, int64_t slice_stride, int k_slice, int m_valid,
+    float* __restrict__ C, int64_t ldc, int64_t slice_stride, int k_slice, int k_total, int m_valid,
     int n_valid, const unsigned* __restrict__ scale_max, FoldSpec fold) {
   constexpr bool kSplit = MODE == kHalfF16x3;
   constexpr int kPlane = kHBM * kHPitch;
@@ -86,7 +86,8 @@ __global__ __launch_bounds__(kHThreads, 2) void gemm_half_kernel(
   const int m0 = (int)(tile / gridDim.x) * kHBM;
   const int n0 = (int)(tile % gridDim.x) * kHBN;
   const int kbeg = blockIdx.z * k_slice;
-  const int nstages = k_slice / kHBK;
+  // the last slice may be shorter (never empty: checked at launch)
+  const int nstages = (min(kbeg + k_slice, k_total) - kbeg) / kHBK;
 
   floatx16 acc[2][2];
 #pragma unroll
@@ -189,17 +190,21 @@ hipError_t launch_mode(const uint16_t* Ah, const uint16_t* Al, int64_t lda, cons
                        int n_valid, const unsigned* scale_max, const FoldSpec* fold,
                        hipStream_t s) {
   const dim3 grid(N / kHBN, M / kHBM, splits);
-  const int k_slice = K / splits;
+  // Slices of k_slice (a multiple of the stage depth), the last one shorter
+  // but never empty.
+  if (splits < 1 || K < kHBK || K % kHBK != 0) return hipErrorInvalidValue;
+  const int k_slice = (K / kHBK + splits - 1) / splits * kHBK;
+  if ((int64_t)(splits - 1) * k_slice >= K) return hipErrorInvalidValue;
   const FoldSpec f = fold ? *fold : FoldSpec{0, nullptr, nullptr, 0, nullptr};
   if (f.part == 1)
     hipLaunchKernelGGL((gemm_half_kernel<MODE, 1>), grid, dim3(kHThreads), 0, s, Ah, Al, lda, Bh,
-                       Bl, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, scale_max, f);
+                       Bl, ldb, C, ldc, slice_stride, k_slice, K, m_valid, n_valid, scale_max, f);
   else if (f.part == 2)
     hipLaunchKernelGGL((gemm_half_kernel<MODE, 2>), grid, dim3(kHThreads), 0, s, Ah, Al, lda, Bh,
-                       Bl, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, scale_max, f);
+                       Bl, ldb, C, ldc, slice_stride, k_slice, K, m_valid, n_valid, scale_max, f);
   else
     hipLaunchKernelGGL((gemm_half_kernel<MODE, 0>), grid, dim3(kHThreads), 0, s, Ah, Al, lda, Bh,
-                       Bl, ldb, C, ldc, slice_stride, k_slice, m_valid, n_valid, scale_max, f);
+                       Bl, ldb, C, ldc, slice_stride, k_slice, K, m_valid, n_valid, scale_max, f);
   return hipGetLastError();
 }
 
