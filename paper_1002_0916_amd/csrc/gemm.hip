@@ -14,12 +14,12 @@
 // block (four 16-byte LDS reads).  Global loads of the next stage are issued
 // before the current stage's MFMAs.
 //
-// Split-K: blockIdx.z selects a contiguous K slice; slice z writes its own
+// Split-K: the grid's z extent counts the K slices; slice z writes its own
 // C plane (C + z * slice_stride), summed afterwards in a fixed order.
 //
-// Shapes: M, N multiples of 128 and K (per slice) a multiple of 32, with the
-// operands zero-padded to those sizes; the store is masked to m < m_valid,
-// n < n_valid.
+// Shapes: M, N multiples of 128 and K a multiple of 32 (the last K slice may
+// be shorter), with the operands zero-padded to those sizes; the store is
+// masked to m < m_valid, n < n_valid.
 #include "cgh_internal.h"
 #include "fold.h"
 
@@ -99,10 +99,16 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_f32_kernel(
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  const int m0 = (int)(tile / gridDim.x) * kBM;
+  // XCD-aware order over (slice, tile row, tile column), slice-major: each
+  // XCD takes a contiguous range, i.e. a compact block of tiles of one K
+  // slice, whose operand rows and columns fit its L2.
+  const unsigned per_slice = gridDim.x * gridDim.y;
+  const unsigned tile = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 per_slice * gridDim.z);
+  const int slice = (int)(tile / per_slice);
+  const int m0 = (int)((tile % per_slice) / gridDim.x) * kBM;
   const int n0 = (int)(tile % gridDim.x) * kBN;
-  const int kbeg = blockIdx.z * k_slice;
+  const int kbeg = slice * k_slice;
   // the last slice may be shorter (never empty: checked at launch)
   const int nstages = (min(kbeg + k_slice, k_total) - kbeg) / kBK;
 
@@ -158,12 +164,12 @@ __global__ __launch_bounds__(kGemmThreads, 2) void gemm_f32_kernel(
 
   if (FOLD) {
     const int64_t npts = (int64_t)gridDim.y * (kBM / 2);
-    float4* dst = fold.out + ((int64_t)blockIdx.z * gridDim.x + n0 / kBN) * npts + m0 / 2;
+    float4* dst = fold.out + ((int64_t)slice * gridDim.x + n0 / kBN) * npts + m0 / 2;
     fold_tile<FOLD>(acc, m0, n0, fold.rec, fold.plain, fold.n_valid, 1.0f, dst,
                     reinterpret_cast<float4*>(&As[0][0]));
     return;
   }
-  float* Cz = C + (int64_t)blockIdx.z * slice_stride;
+  float* Cz = C + (int64_t)slice * slice_stride;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll

@@ -17,8 +17,9 @@
 // tile with 4 waves (64 x 64 each = 2 x 2 blocks); K advances 32 per stage
 // through double-buffered LDS tiles [row][k] with rows padded to 40 elements
 // (80 bytes: the 16-byte fragment reads of 16 consecutive lanes hit distinct
-// banks).  Split-K over blockIdx.z as in the FP32 kernel.  M, N multiples of
-// 128; K per slice a multiple of 32; stores masked to m < m_valid, n < n_valid.
+// banks).  Split-K over the grid's z extent as in the FP32 kernel.  M, N
+// multiples of 128; K a multiple of 32 (the last K slice may be shorter);
+// stores masked to m < m_valid, n < n_valid.
 #include <stdint.h>
 
 #include "cgh_internal.h"
@@ -82,10 +83,16 @@ __global__ __launch_bounds__(kHThreads, 2) void gemm_half_kernel(
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  const int m0 = (int)(tile / gridDim.x) * kHBM;
+  // XCD-aware order over (slice, tile row, tile column), slice-major: each
+  // XCD takes a contiguous range, i.e. a compact block of tiles of one K
+  // slice, whose operand rows and columns fit its L2.
+  const unsigned per_slice = gridDim.x * gridDim.y;
+  const unsigned tile = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 per_slice * gridDim.z);
+  const int slice = (int)(tile / per_slice);
+  const int m0 = (int)((tile % per_slice) / gridDim.x) * kHBM;
   const int n0 = (int)(tile % gridDim.x) * kHBN;
-  const int kbeg = blockIdx.z * k_slice;
+  const int kbeg = slice * k_slice;
   // the last slice may be shorter (never empty: checked at launch)
   const int nstages = (min(kbeg + k_slice, k_total) - kbeg) / kHBK;
 
@@ -164,12 +171,12 @@ __global__ __launch_bounds__(kHThreads, 2) void gemm_half_kernel(
   const float alpha = scale_max ? pow2_scale(*scale_max) : 1.0f;
   if (FOLD) {
     const int64_t npts = (int64_t)gridDim.y * (kHBM / 2);
-    float4* dst = fold.out + ((int64_t)blockIdx.z * gridDim.x + n0 / kHBN) * npts + m0 / 2;
+    float4* dst = fold.out + ((int64_t)slice * gridDim.x + n0 / kHBN) * npts + m0 / 2;
     fold_tile<FOLD>(acc, m0, n0, fold.rec, fold.plain, fold.n_valid, alpha, dst,
                     reinterpret_cast<float4*>(&smem[0][0][0]));
     return;
   }
-  float* Cz = C + (int64_t)blockIdx.z * slice_stride;
+  float* Cz = C + (int64_t)slice * slice_stride;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
