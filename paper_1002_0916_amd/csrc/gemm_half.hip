@@ -15,9 +15,8 @@
 // accumulator register r of lane l is C[(r / 4) * 8 + (l / 32) * 4 + r % 4]
 // [l % 32] (layout checked on the device).  The workgroup computes a 128 x 128
 // tile with 4 waves (64 x 64 each = 2 x 2 blocks); K advances 32 per stage
-// through double-buffered LDS tiles [row][k] with rows padded to 40 elements
-// (80 bytes: the 16-byte fragment reads of 16 consecutive lanes hit distinct
-// banks).  Split-K over the grid's z extent as in the FP32 kernel.  M, N
+// through double-buffered LDS tiles [row][k] (64-byte rows, chunk-swizzled:
+// lds_at).  Split-K over the grid's z extent as in the FP32 kernel.  M, N
 // multiples of 128; K a multiple of 32 (the last K slice may be shorter);
 // stores masked to m < m_valid, n < n_valid.
 #include <stdint.h>
@@ -33,7 +32,16 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kHBM = 128, kHBN = 128, kHBK = 32, kHPitch = kHBK + 8;
+constexpr int kHBM = 128, kHBN = 128, kHBK = 32, kHPitch = kHBK;
+
+// LDS tiles are [row][k] with 64-byte rows (no padding) and the four 16-byte
+// chunks of a row permuted by chunk ^ ((row / 4) % 4).  Both access patterns
+// then spread over all 64 banks: a fragment read (16 lanes: 16 consecutive
+// rows, one chunk) and a tile store (16 lanes: 4 consecutive rows, all four
+// chunks).
+__device__ __forceinline__ int lds_at(int row, int chunk) {
+  return row * kHPitch + ((chunk ^ ((row >> 2) & 3)) << 3);
+}
 constexpr int kHThreads = 256;
 
 // This thread's share of a 128 x 32 plane tile: 16-byte chunks c = t and
@@ -56,9 +64,8 @@ __device__ __forceinline__ Half16 load_plane(const uint16_t* __restrict__ src, i
 
 __device__ __forceinline__ void store_plane(uint16_t* __restrict__ lds, const Half16& r) {
   const int t = threadIdx.x;
-  uint16_t* p = lds + (t / 4) * kHPitch + (t & 3) * 8;
-  *reinterpret_cast<uint4*>(p) = r.lo8;
-  *reinterpret_cast<uint4*>(p + 64 * kHPitch) = r.hi8;
+  *reinterpret_cast<uint4*>(lds + lds_at(t / 4, t & 3)) = r.lo8;
+  *reinterpret_cast<uint4*>(lds + lds_at(t / 4 + 64, t & 3)) = r.hi8;
 }
 
 template <int MODE>
@@ -119,7 +126,6 @@ __global__ __launch_bounds__(kHThreads, 2) void gemm_half_kernel(
   }
   __syncthreads();
 
-  const int kq = (lane >> 5) * 8;
   for (int s = 0; s < nstages; ++s) {
     const int buf = s & 1;
     if (s + 1 < nstages) {
@@ -136,8 +142,8 @@ __global__ __launch_bounds__(kHThreads, 2) void gemm_half_kernel(
       uint4 fah[2], fbh[2], fal[2], fbl[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const int ra = (wm * 64 + i * 32 + (lane & 31)) * kHPitch + t * 16 + kq;
-        const int rb = (wn * 64 + i * 32 + (lane & 31)) * kHPitch + t * 16 + kq;
+        const int ra = lds_at(wm * 64 + i * 32 + (lane & 31), 2 * t + (lane >> 5));
+        const int rb = lds_at(wn * 64 + i * 32 + (lane & 31), 2 * t + (lane >> 5));
         fah[i] = *reinterpret_cast<const uint4*>(&smem[buf][0][ra]);
         fbh[i] = *reinterpret_cast<const uint4*>(&smem[buf][1][rb]);
         if (kSplit) {
