@@ -12,6 +12,8 @@ from fractions import Fraction
 
 import numpy as np
 import pytest
+from hypothesis import given, settings
+from hypothesis import strategies as st
 
 from paper_1002_0916_amd import workloads as W
 
@@ -112,6 +114,25 @@ def test_against_live_brute_force(oracle_mod):
     I = oracle_mod.forward(*c.astuple(), 6, 5)
     ref = np.array([[float(v) for v in row] for row in brute.hologram(*c.astuple(), 6, 5, P, LAM)])
     assert np.max(np.abs(I - ref)) < 1e-12
+
+
+@settings(max_examples=30, deadline=None, derandomize=True)
+@given(seed=st.integers(0, 2 ** 31 - 1), n=st.integers(1, 4), nx=st.integers(1, 6),
+       ny=st.integers(1, 5), z=st.sampled_from([1e-4, 1e-3, 1e-2, 0.5]),
+       amp=st.sampled_from([1e-6, 1.0, 1e6]))
+def test_random_clouds_against_brute_force(oracle_mod, seed, n, nx, ny, z, amp):
+    """Random tiny clouds (points up to 3 px outside the grid, depths giving
+    phases from ~1e-2 to ~500 rad, amplitudes over 12 decades): the oracle
+    matches the 50-digit brute force within FP64 rounding of the phase."""
+    from oracle import brute
+
+    c = W.random_cloud(seed, n, nx, ny, zlo=z, zhi=2 * z, alo=-amp, ahi=amp, margin=3)
+    I = oracle_mod.forward(*c.astuple(), nx, ny)
+    ref = np.array([[float(v) for v in row]
+                    for row in brute.hologram(*c.astuple(), nx, ny, P, LAM)])
+    # |d theta| <= a few ulp(theta) with theta <= 500 rad: < 1e-12 per unit amplitude
+    bound = 1e-12 * float(np.sum(np.abs(c.a.astype(np.float64))))
+    assert np.max(np.abs(I - ref)) <= bound
 
 
 def test_integer_translation(oracle_mod):
