@@ -18,8 +18,8 @@
 // Per interaction that leaves the phase, sin and cos, and three fused
 // multiply-adds with G taken straight from an SGPR.
 //
-// Second pass: kFinSlices threads per point add interleaved subsets of the
-// region partials in region order, then one thread adds the slice sums in
+// Second pass: kAdjFinSlices threads per point add interleaved subsets of
+// the region partials in region order, then one thread adds the slice sums in
 // slice order (a fixed tree, so the result is bitwise reproducible), in FP64,
 // and applies the per-point factors 2 A_j P_j and A_j P_j / z_j.
 #include <map>
@@ -140,46 +140,38 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
   partial[(int64_t)run * npad + j] = make_float4(Sc0 + Sc1, Sx, Sy, Sr);
 }
 
-__global__ __launch_bounds__(kWave* kFinSlices) void adj_finalize_kernel(
+__global__ __launch_bounds__(kAdjFinPoints* kAdjFinSlices) void adj_finalize_kernel(
     const float4* __restrict__ partial, int regions, int64_t npad, int64_t n,
     const float* __restrict__ z, const float* __restrict__ a, double pitch, double wavelength,
     float* __restrict__ gx, float* __restrict__ gy, float* __restrict__ gz,
     float* __restrict__ ga) {
-  __shared__ double part[kFinSlices][4][kWave];
-  const int lane = threadIdx.x;
+  __shared__ double part[kAdjFinSlices][4][kAdjFinPoints];
+  const int pt = threadIdx.x;
   const int slice = threadIdx.y;
-  const int64_t j = (int64_t)blockIdx.x * kWave + lane;
+  const int64_t j = (int64_t)blockIdx.x * kAdjFinPoints + pt;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   if (j < npad) {
-    // Regions slice, slice + kFinSlices, ... in increasing order.
-    int r = slice;
-    for (; r + 3 * kFinSlices < regions; r += 4 * kFinSlices) {
-      const float4 v0 = partial[(int64_t)r * npad + j];
-      const float4 v1 = partial[(int64_t)(r + kFinSlices) * npad + j];
-      const float4 v2 = partial[(int64_t)(r + 2 * kFinSlices) * npad + j];
-      const float4 v3 = partial[(int64_t)(r + 3 * kFinSlices) * npad + j];
-      s0 += (double)v0.x; s1 += (double)v0.y; s2 += (double)v0.z; s3 += (double)v0.w;
-      s0 += (double)v1.x; s1 += (double)v1.y; s2 += (double)v1.z; s3 += (double)v1.w;
-      s0 += (double)v2.x; s1 += (double)v2.y; s2 += (double)v2.z; s3 += (double)v2.w;
-      s0 += (double)v3.x; s1 += (double)v3.y; s2 += (double)v3.z; s3 += (double)v3.w;
-    }
-    for (; r < regions; r += kFinSlices) {
+    // Regions slice, slice + kAdjFinSlices, ... in increasing order.
+    for (int r = slice; r < regions; r += kAdjFinSlices) {
       const float4 v = partial[(int64_t)r * npad + j];
-      s0 += (double)v.x; s1 += (double)v.y; s2 += (double)v.z; s3 += (double)v.w;
+      s0 += (double)v.x;
+      s1 += (double)v.y;
+      s2 += (double)v.z;
+      s3 += (double)v.w;
     }
   }
-  part[slice][0][lane] = s0;
-  part[slice][1][lane] = s1;
-  part[slice][2][lane] = s2;
-  part[slice][3][lane] = s3;
+  part[slice][0][pt] = s0;
+  part[slice][1][pt] = s1;
+  part[slice][2][pt] = s2;
+  part[slice][3][pt] = s3;
   __syncthreads();
   if (slice != 0 || j >= n) return;
   double Sc = 0.0, Sx = 0.0, Sy = 0.0, Sr = 0.0;
-  for (int k = 0; k < kFinSlices; ++k) {
-    Sc += part[k][0][lane];
-    Sx += part[k][1][lane];
-    Sy += part[k][2][lane];
-    Sr += part[k][3][lane];
+  for (int k = 0; k < kAdjFinSlices; ++k) {
+    Sc += part[k][0][pt];
+    Sx += part[k][1][pt];
+    Sy += part[k][2][pt];
+    Sr += part[k][3][pt];
   }
   const double zj = (double)z[j];
   const double aj = (double)a[j];
@@ -261,9 +253,10 @@ hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* g,
 hipError_t launch_adj_finalize(const Plan& p, const Workspace& w, const float* z, const float* a,
                                double pitch, double wavelength, int runs, float* gx, float* gy,
                                float* gz, float* ga, hipStream_t s) {
-  hipLaunchKernelGGL(adj_finalize_kernel, dim3((unsigned)((p.n + kWave - 1) / kWave)),
-                     dim3(kWave, kFinSlices), 0, s, (const float4*)w.partial, runs, p.npad, p.n,
-                     z, a, pitch, wavelength, gx, gy, gz, ga);
+  hipLaunchKernelGGL(adj_finalize_kernel,
+                     dim3((unsigned)((p.n + kAdjFinPoints - 1) / kAdjFinPoints)),
+                     dim3(kAdjFinPoints, kAdjFinSlices), 0, s, (const float4*)w.partial, runs,
+                     p.npad, p.n, z, a, pitch, wavelength, gx, gy, gz, ga);
   return hipGetLastError();
 }
 

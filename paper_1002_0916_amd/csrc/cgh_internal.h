@@ -83,8 +83,13 @@ constexpr int kAdjMinRun = 8;
 #define CGH_ADJ_ROUNDS 3
 #endif
 constexpr int kAdjRounds = CGH_ADJ_ROUNDS;
-// Second pass: kFinSlices threads per point add interleaved region subsets.
+// Second passes: kFinSlices threads per point add interleaved subsets of the
+// partial planes (the separable finalize), and the direct adjoint's finalize
+// spreads its many run partials over kAdjFinSlices threads for each of
+// kAdjFinPoints points per workgroup.
 constexpr int kFinSlices = 16;
+constexpr int kAdjFinPoints = 16;
+constexpr int kAdjFinSlices = 64;
 
 // Point records, all produced on the device by the prep kernel from the FP32
 // inputs with FP64 arithmetic.
