@@ -205,3 +205,19 @@ def test_binding_validates_tensors():
         B.forward(x, x, x, x, 8, 8)  # CPU tensors are refused (no CPU path)
     with pytest.raises(ValueError):
         B.variant_id("fastest")
+
+
+def test_header_compiles_and_links_as_c(tmp_path, lib):
+    """include/cgh.h is self-contained C: the plain-C consumer builds with gcc
+    against it and links against libcgh.so (run on the GPU in
+    test_gpu_c_abi.py)."""
+    import importlib.util
+    import subprocess
+
+    spec = importlib.util.spec_from_file_location(
+        "c_abi_build", os.path.join(ROOT, "tests", "c_abi", "build.py"))
+    c_build = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(c_build)
+    out = str(tmp_path / "check")
+    subprocess.run(c_build.command(out), check=True)
+    assert os.path.exists(out)
