@@ -8,10 +8,20 @@ yields dL/dx, dL/dy, dL/dz, dL/dA of L = 0.5 ||I - T||^2.  Inputs are seeded
 synthetic clouds already resident in HBM.
 
 Prints ONE JSON line: throughput in G point-pixel interactions per second
-(N * Nx * Ny / step time), the roofline record of the dominant kernel (the
-adjoint) from HIP events recorded around it, accuracy against the FP64 GPU
-forward, and the FP64 CPU oracle's rate on a bounded sample of the same
-workload (the cpu_baseline leg, the only part that touches the oracle).
+(N * Nx * Ny / step time) of the compensated variant (the paper's method:
+one native cosine per interaction), the roofline record of the dominant
+kernel (the adjoint) from HIP events recorded around it, accuracy against the
+FP64 GPU forward, and the FP64 CPU oracle's rate on a bounded sample of the
+same workload (the cpu_baseline leg, the only part that touches the oracle).
+Under "variants" the same step is reported for every variant (plain,
+compensated, the FP32 and 16-bit separable forms): step time eager and as a
+replayed HIP graph, mean / median / min kernel times, roofline fractions and
+the errors against FP64 (forward) and the compensated adjoint.
+
+Other modes print one report line each: --workload (the other workload
+shapes, every variant, and the Adam fitting loop for fit4k), --sweep (the
+Table 1 N-sweep), --oracle-timing (the oracle per workload, serial and on all
+cores), --copy-bytes (a plain copy, the reference for hardware byte counters).
 """
 from __future__ import annotations
 
