@@ -46,11 +46,16 @@ TRANS_SLOTS = 2
 #  adj plain        r2 (fma), Prev*r2, fract, sin, cos, Sc fma,
 #                   G*sin folded into column and row sums (2 fma)     = 6 + 4
 #  adj compensated  X+Y add, sin, cos, Sc fma, column/row sums (2)    = 4 + 4
+#  fwd recurrence   Gamma += delta, cos, acc fma (delta += Delta is
+#                   shared by the rows of a lane; seeds are overhead) = 2 + 2
+# The recurrence variant's backward is the plain adjoint kernel.
 SLOTS = {
     "fwd_plain": 5 + TRANS_SLOTS,
     "fwd_compensated": 2 + TRANS_SLOTS,
+    "fwd_recurrence": 2 + TRANS_SLOTS,
     "adj_plain": 6 + 2 * TRANS_SLOTS,
     "adj_compensated": 4 + 2 * TRANS_SLOTS,
+    "adj_recurrence": 6 + 2 * TRANS_SLOTS,
 }
 # The same work if every packable FP32 add/mul/fma ran as packed math (two
 # lanes per slot; fract and the transcendentals do not pack).  Packed FP32 is
@@ -59,8 +64,10 @@ SLOTS = {
 SLOTS_PACKED = {
     "fwd_plain": 4 / 2 + 1 + TRANS_SLOTS,
     "fwd_compensated": 2 / 2 + TRANS_SLOTS,
+    "fwd_recurrence": 2 / 2 + TRANS_SLOTS,
     "adj_plain": 5 / 2 + 1 + 2 * TRANS_SLOTS,
     "adj_compensated": 4 / 2 + 2 * TRANS_SLOTS,
+    "adj_recurrence": 5 / 2 + 1 + 2 * TRANS_SLOTS,
 }
 # The separable variant is a different algorithm, bound by the FP32 matrix
 # cores (dense MFMA FP32 peak 157.3 TFLOP/s): the forward is one GEMM of
@@ -73,8 +80,8 @@ PEAK_MFMA_F32 = 157.3e12
 PEAK_MFMA_F16 = 2.5e15
 MFMA_FLOPS = {"separable": (4, 8, PEAK_MFMA_F32), "separable_f16x3": (12, 24, PEAK_MFMA_F16),
               "separable_f16": (4, 8, PEAK_MFMA_F16), "separable_bf16": (4, 8, PEAK_MFMA_F16)}
-ALL_VARIANTS = ("compensated", "plain", "separable", "separable_f16x3", "separable_f16",
-                "separable_bf16")
+ALL_VARIANTS = ("compensated", "plain", "recurrence", "separable", "separable_f16x3",
+                "separable_f16", "separable_bf16")
 
 
 def peak_interactions(key):
@@ -149,9 +156,9 @@ def measured_traffic(kernel):
     return rec["traffic_bytes"]
 
 
-FWD_KERNEL = {"plain": 0, "compensated": 1}
-ADJ_KERNEL = {"plain": 3, "compensated": 4}
-for _v in ALL_VARIANTS[2:]:
+FWD_KERNEL = {"plain": 0, "compensated": 1, "recurrence": 7}
+ADJ_KERNEL = {"plain": 3, "compensated": 4, "recurrence": 3}
+for _v in MFMA_FLOPS:
     FWD_KERNEL[_v], ADJ_KERNEL[_v] = 5, 6
 
 
@@ -258,7 +265,7 @@ def main():
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        for k in range(B.KERNEL_ADJ_SEPARABLE + 1):
+        for k in range(B.KERNEL_COUNT):
             B.profile_read(k)  # clear
         B.profile_enable(True)
         ms, wall = timed_steps(step, args.steps, torch)
@@ -650,7 +657,8 @@ def report_workload(args):
 
 def report_sweep(args):
     """Forward kernel time against N at 1920x1024 (the Table 1 shapes and
-    beyond), both FP32 variants; the paper's HD5850 times are context."""
+    beyond) for the direct FP32 variants, the recurrence of Eq. (2) (the
+    kernel Table 1 times) among them; the paper's HD5850 times are context."""
     import torch
 
     from paper_1002_0916_amd import binding as B
@@ -666,6 +674,7 @@ def report_sweep(args):
         I = torch.empty((1024, 1920), dtype=torch.float32, device=dev)
         rec = {"n": n, "paper_hd5850_ms": paper_ms.get(n)}
         for variant, k in (("plain", B.KERNEL_FWD_PLAIN),
+                           ("recurrence", B.KERNEL_FWD_RECURRENCE),
                            ("compensated", B.KERNEL_FWD_COMPENSATED)):
             ms = _kernel_ms(B, torch, lambda: B.forward(x, y, z, a, 1920, 1024, variant=variant,
                                                         out=I), k, 10)

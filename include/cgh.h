@@ -63,6 +63,12 @@
  *                       BF16 round each operand once (unit roundoff 2^-11 and
  *                       2^-8), so the forward error stays below about
  *                       2 u sum |A_j| (u = 2^-11, 2^-8).
+ *      CGH_RECURRENCE   the forward by the two recurrence formulas of Eq. (2)
+ *                       (Section 2.1): along a row Gamma_n = Gamma_{n-1} +
+ *                       delta_{n-1}, delta_n = delta_{n-1} + Delta, each lane
+ *                       producing a few consecutive pixels from the plain
+ *                       FP32 phase Gamma_0 of the first (same accuracy class
+ *                       as CGH_PLAIN).  Its backward is CGH_PLAIN's adjoint.
  *    FP64 appears only in the per-point precompute of P_j / (2 pi) and its
  *    hi/lo split (and in cgh_forward_f64).
  */
@@ -89,6 +95,7 @@ extern "C" {
 #define CGH_SEPARABLE_F16X3 3
 #define CGH_SEPARABLE_F16 4
 #define CGH_SEPARABLE_BF16 5
+#define CGH_RECURRENCE 6
 
 /* Operations, for cgh_workspace_bytes. */
 #define CGH_OP_FORWARD 0
@@ -103,7 +110,8 @@ extern "C" {
 #define CGH_KERNEL_ADJ_COMPENSATED 4
 #define CGH_KERNEL_FWD_SEPARABLE 5 /* the forward GEMM (every separable variant) */
 #define CGH_KERNEL_ADJ_SEPARABLE 6 /* both adjoint GEMMs, one event pair */
-#define CGH_KERNEL_COUNT 7
+#define CGH_KERNEL_FWD_RECURRENCE 7
+#define CGH_KERNEL_COUNT 8
 
 /*
  * Bytes of device workspace that `op` (CGH_OP_*) needs for n points on an
@@ -120,8 +128,8 @@ size_t cgh_workspace_bytes(int64_t n, int32_t nx, int32_t ny, int32_t variant, i
  *                and amplitudes A_j.
  *   hologram     device float32[ny][nx], overwritten with I.  n = 0 writes
  *                zeros.
- *   variant      CGH_PLAIN, CGH_COMPENSATED, CGH_SEPARABLE or one of the
- *                half-precision separable variants.
+ *   variant      CGH_PLAIN, CGH_COMPENSATED, CGH_SEPARABLE, one of the
+ *                half-precision separable variants, or CGH_RECURRENCE.
  */
 int cgh_forward(const float* x, const float* y, const float* z, const float* a, int64_t n,
                 int32_t nx, int32_t ny, double pitch, double wavelength, int32_t variant,
@@ -156,7 +164,7 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
 const char* cgh_strerror(int status);
 
 /* Library ABI version (major * 100 + minor): 101 adds the half-precision
- * separable variants. */
+ * separable variants, 102 CGH_RECURRENCE. */
 int cgh_version(void);
 
 /*

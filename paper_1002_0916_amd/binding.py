@@ -29,15 +29,19 @@ LIB_PATH = os.path.join(HERE, "libcgh.so")
 CGH_OK, CGH_EINVAL, CGH_EWORKSPACE, CGH_EHIP = 0, 1, 2, 3
 PLAIN, COMPENSATED, SEPARABLE = 0, 1, 2
 SEPARABLE_F16X3, SEPARABLE_F16, SEPARABLE_BF16 = 3, 4, 5
+RECURRENCE = 6
 SEPARABLE_IDS = (SEPARABLE, SEPARABLE_F16X3, SEPARABLE_F16, SEPARABLE_BF16)
 OP_FORWARD, OP_FORWARD_F64, OP_BACKWARD = 0, 1, 2
 KERNEL_FWD_PLAIN, KERNEL_FWD_COMPENSATED, KERNEL_FWD_F64 = 0, 1, 2
 KERNEL_ADJ_PLAIN, KERNEL_ADJ_COMPENSATED = 3, 4
 KERNEL_FWD_SEPARABLE, KERNEL_ADJ_SEPARABLE = 5, 6
+KERNEL_FWD_RECURRENCE = 7
+KERNEL_COUNT = 8
 
 VARIANTS = {"plain": PLAIN, "fast": PLAIN, "compensated": COMPENSATED, "comp": COMPENSATED,
             "separable": SEPARABLE, "separable_f16x3": SEPARABLE_F16X3,
-            "separable_f16": SEPARABLE_F16, "separable_bf16": SEPARABLE_BF16}
+            "separable_f16": SEPARABLE_F16, "separable_bf16": SEPARABLE_BF16,
+            "recurrence": RECURRENCE}
 
 EXPORTED = ("cgh_workspace_bytes", "cgh_forward", "cgh_forward_f64", "cgh_backward",
             "cgh_strerror", "cgh_version", "cgh_profile_enable", "cgh_profile_read",

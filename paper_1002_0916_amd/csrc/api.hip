@@ -46,7 +46,41 @@ inline int gemm_splits(int64_t tiles, int64_t k) {
   return best;
 }
 
-inline bool valid_variant(int32_t v) { return v >= CGH_PLAIN && v <= CGH_SEPARABLE_BF16; }
+// Shape of the recurrence forward: K pixels x R rows per lane, from the
+// instantiated set K in {4, 6, 8}, R in {1, 2, 4}.  The choice minimises a
+// time model in issue slots per SIMD: the workgroups each of the 256 CUs runs
+// (ceil(workgroups / 256); a workgroup is one wave per SIMD) times the
+// interactions per lane per point (K R) times the slots per interaction,
+//   4 + 1/R + (4 R + 7) / (K R)
+// (cosine 2, the Gamma add and the accumulate per interaction; delta's add
+// once per column step for R rows; dx, dx^2, delta_0 and Delta once per point
+// and lane; Gamma_0 once per row).  CGH_REC_SHAPE = 10 K + R forces a shape
+// (tuning builds only).
+inline void rec_shape(int32_t nx, int32_t ny, int32_t& k_out, int32_t& r_out) {
+#ifdef CGH_REC_SHAPE
+  (void)nx;
+  (void)ny;
+  k_out = CGH_REC_SHAPE / 10;
+  r_out = CGH_REC_SHAPE % 10;
+#else
+  static const int kShapes[][2] = {{8, 4}, {8, 2}, {8, 1}, {6, 4}, {6, 2},
+                                   {6, 1}, {4, 4}, {4, 2}, {4, 1}};
+  double best = 0.0;
+  for (const auto& sh : kShapes) {
+    const int K = sh[0], R = sh[1];
+    const int64_t wgs = ceil_div(nx, (int64_t)kWave * K) * ceil_div(ny, (int64_t)kRecWaves * R);
+    const double slots = 4.0 + 1.0 / R + (4.0 * R + 7.0) / (K * R);
+    const double t = (double)ceil_div(wgs, 256) * K * R * slots;
+    if (best == 0.0 || t < best) {
+      best = t;
+      k_out = K;
+      r_out = R;
+    }
+  }
+#endif
+}
+
+inline bool valid_variant(int32_t v) { return v >= CGH_PLAIN && v <= CGH_RECURRENCE; }
 
 // The 16-bit GEMM format of a half-precision separable variant, or -1.
 inline int half_mode(int32_t v) {
@@ -78,6 +112,9 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   p.fwd_gy = (int32_t)ceil_div(ny, kFwdRowsPerWG);
   p.comp_gy = (int32_t)ceil_div(ny, kCompRowsPerWG);
   p.groups = p.comp_gy * kCompWaves;
+  rec_shape(nx, ny, p.rec_k, p.rec_r);
+  p.rec_gx = (int32_t)ceil_div(nx, (int64_t)kWave * p.rec_k);
+  p.rec_gy = (int32_t)ceil_div(ny, (int64_t)kRecWaves * p.rec_r);
   p.ngroups = (int32_t)(p.npad / kWave);
   p.nsx = (int32_t)ceil_div(nx, kAdjCols);
   p.strip_rows = (int64_t)p.nsx * ny;
@@ -402,6 +439,10 @@ int cgh_forward(const float* x, const float* y, const float* z, const float* a, 
     const EventPair ev = profile_begin(CGH_KERNEL_FWD_COMPENSATED, s);
     e = launch_fwd_comp(p, w, hologram, s);
     profile_end(CGH_KERNEL_FWD_COMPENSATED, ev, s);
+  } else if (variant == CGH_RECURRENCE) {
+    const EventPair ev = profile_begin(CGH_KERNEL_FWD_RECURRENCE, s);
+    e = launch_fwd_rec(p, w, hologram, s);
+    profile_end(CGH_KERNEL_FWD_RECURRENCE, ev, s);
   } else {
     const EventPair ev = profile_begin(CGH_KERNEL_FWD_PLAIN, s);
     e = launch_fwd_plain(p, w, hologram, s);
@@ -487,7 +528,7 @@ const char* cgh_strerror(int status) {
   }
 }
 
-int cgh_version(void) { return 101; }
+int cgh_version(void) { return 102; }
 
 int cgh_profile_enable(int32_t on) {
   Profiler& P = profiler();

@@ -64,6 +64,15 @@ static_assert(kWave % kCompWaves == 0, "x-phase fill splits the 64 columns over 
 static_assert(kTile % (2 * kCompUnroll) == 0, "tiles hold whole ping-pong group pairs");
 constexpr int kPointPad = 64;
 
+// Recurrence forward (Eq. (2)): lane l of a wave covers kRecK consecutive
+// pixels of kRecR rows, a workgroup kRecWaves waves stacked in y; points are
+// taken kRecUnroll at a time (scalar loads one group ahead).  (K, R) comes
+// from a small set of instantiations chosen per shape by rec_shape().
+constexpr int kRecWaves = 4;
+constexpr int kRecThreads = kRecWaves * kWave;
+constexpr int kRecUnroll = 4;
+static_assert(kPointPad % (2 * kRecUnroll) == 0, "point padding holds whole group pairs");
+
 // ---------------------------------------------------------------- adjoint --
 // An adjoint wave holds 64 points (one per lane) and sweeps a run of
 // strip-rows: the hologram is cut into strips of kAdjCols columns, and the
@@ -136,6 +145,7 @@ struct Plan {
   int32_t variant, op;
   // forward
   int32_t fwd_gx, fwd_gy, comp_gy, groups;
+  int32_t rec_k, rec_r, rec_gx, rec_gy;  // recurrence forward shape and grid
   // adjoint: runs of strip-rows per point group (regions = the most runs the
   // partial buffer holds; the launch may use fewer)
   int32_t nsx, regions, ngroups;
@@ -163,6 +173,7 @@ hipError_t launch_fill_zero_f64(double* p, int64_t count, hipStream_t s);
 hipError_t launch_ytab(const Plan& p, const Workspace& w, hipStream_t s);
 hipError_t launch_fwd_plain(const Plan& p, const Workspace& w, float* out, hipStream_t s);
 hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s);
+hipError_t launch_fwd_rec(const Plan& p, const Workspace& w, float* out, hipStream_t s);
 hipError_t launch_fwd_f64(const Plan& p, const Workspace& w, double* out, hipStream_t s);
 hipError_t launch_pad_g(const Plan& p, const float* g, float* gpad, hipStream_t s);
 // Optional epilogue of the adjoint GEMMs (fold.h): instead of storing its

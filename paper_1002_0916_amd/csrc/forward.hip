@@ -55,6 +55,95 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_plain_kernel(const float4* __
   }
 }
 
+// Recurrence FP32, Eq. (2) (Section 2.1): along a row the phase of pixel
+// x_h + n follows from two additions, Gamma_n = Gamma_{n-1} + delta_{n-1} and
+// delta_n = delta_{n-1} + Delta, from Gamma_0 = P r^2 at x_h,
+// delta_0 = P (2 (x_h - x_j) + 1) and Delta = 2 P (here in revolutions, P ->
+// Prev).  Lane l covers the K consecutive pixels x0 + K l ... x0 + K l + K - 1
+// of R rows (the paper's work-item covers eight consecutive pixels of one
+// row).  delta and Delta depend on the column only, so the lane's R rows
+// share them: per point the lane forms dx, delta_0 and Delta once and
+// Gamma_0 = fract(Prev r^2) (the plain phase) once per row, and per
+// interaction the recurrence costs one add for Gamma (plus 1/R of an add for
+// delta) before the native cosine and the accumulate.  Gamma_0 is in [0, 1)
+// and delta_0, Delta are reduced mod 1 (exactly; cos is 1-periodic in
+// revolutions), so |Gamma_n| < 1 + n (1 + n) stays well inside the cosine's
+// exact-reduction range without a fract per step.  Points are read four at a
+// time through scalar loads (the paper unrolls four points per iteration),
+// one group ahead of their use.
+template <int K, int R>
+__global__ __launch_bounds__(kRecThreads) void fwd_rec_kernel(const float4* __restrict__ rec,
+                                                              int npad, int nx, int ny,
+                                                              float* __restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  // Row blocks run along the grid's x dimension (up to 2^20 / 4 of them),
+  // column blocks along y.
+  const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int by = (int)(tile % gridDim.x), bx = (int)(tile / gridDim.x);
+  const int x0 = (bx * kWave + lane) * K;
+  const int y0 = (by * kRecWaves + wave) * R;
+  const float xh = (float)x0;
+  float acc[R][K];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int n = 0; n < K; ++n) acc[i][n] = 0.0f;
+
+  auto point = [&](const float4& r) {
+    const float dx = xh - r.x;
+    const float dx2 = dx * dx;
+    float d = fract(r.z * __builtin_fmaf(2.0f, dx, 1.0f));
+    const float D = fract(r.z + r.z);
+    float g[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const float dy = (float)(y0 + i) - r.y;
+      g[i] = fract(r.z * __builtin_fmaf(dy, dy, dx2));
+    }
+#pragma unroll
+    for (int n = 0; n < K; ++n) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) acc[i][n] = __builtin_fmaf(r.w, cos_rev(g[i]), acc[i][n]);
+      if (n + 1 < K) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) g[i] += d;
+        d += D;
+      }
+    }
+  };
+  // Two ping-pong groups of records in SGPRs; the next group's loads are
+  // issued after the first point of the current one (whose use waits for
+  // every outstanding scalar load), so the other points cover their latency.
+  // The last group re-reads itself (in bounds).
+  auto load = [&](int j, float4* dst) {
+#pragma unroll
+    for (int u = 0; u < kRecUnroll; ++u) dst[u] = rec[j + u];
+  };
+  auto group = [&](int j, const float4* cur, float4* nxt) {
+    point(cur[0]);
+    __builtin_amdgcn_sched_barrier(0);
+    load(min(j + kRecUnroll, npad - kRecUnroll), nxt);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 1; u < kRecUnroll; ++u) point(cur[u]);
+  };
+  float4 A[kRecUnroll], B[kRecUnroll];
+  load(0, A);
+  for (int j = 0; j < npad; j += 2 * kRecUnroll) {
+    group(j, A, B);
+    group(j + kRecUnroll, B, A);
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    if (y0 + i >= ny) continue;
+    float* row = out + (int64_t)(y0 + i) * nx;
+#pragma unroll
+    for (int n = 0; n < K; ++n)
+      if (x0 + n < nx) row[x0 + n] = acc[i][n];
+  }
+}
+
 // Compensated FP32: the phase separates exactly as X_j(x_h) + Y_j(y_h) with
 // X_j(x_h) = Prev (x_h - x_j)^2 and Y_j(y_h) = Prev (y_h - y_j)^2.  Each part
 // is formed on the integer pixel grid as a compensated split product reduced
@@ -81,7 +170,6 @@ __global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(const float* __r
   const int col = bx * kWave + lane;
   const int col0 = bx * kWave;
   const int grp = by * kCompWaves + wave;
-  const float xh = (float)col;
   const float* __restrict__ yt = ytab + (int64_t)grp * npad * kCompRows;
   const int ntiles = npad / kTile;
   constexpr int kColsPerWave = kWave / kCompWaves;
@@ -189,6 +277,32 @@ hipError_t launch_fwd_plain(const Plan& p, const Workspace& w, float* out, hipSt
   hipLaunchKernelGGL(fwd_plain_kernel, dim3(p.fwd_gx, p.fwd_gy), dim3(kFwdThreads), 0, s,
                      (const float4*)w.plain, (int)p.npad, p.nx, p.ny, out);
   return hipGetLastError();
+}
+
+namespace {
+
+template <int K, int R>
+hipError_t launch_rec(const Plan& p, const Workspace& w, float* out, hipStream_t s) {
+  hipLaunchKernelGGL((fwd_rec_kernel<K, R>), dim3(p.rec_gy, p.rec_gx), dim3(kRecThreads), 0, s,
+                     (const float4*)w.plain, (int)p.npad, p.nx, p.ny, out);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fwd_rec(const Plan& p, const Workspace& w, float* out, hipStream_t s) {
+  switch (p.rec_k * 10 + p.rec_r) {
+    case 41: return launch_rec<4, 1>(p, w, out, s);
+    case 42: return launch_rec<4, 2>(p, w, out, s);
+    case 44: return launch_rec<4, 4>(p, w, out, s);
+    case 61: return launch_rec<6, 1>(p, w, out, s);
+    case 62: return launch_rec<6, 2>(p, w, out, s);
+    case 64: return launch_rec<6, 4>(p, w, out, s);
+    case 81: return launch_rec<8, 1>(p, w, out, s);
+    case 82: return launch_rec<8, 2>(p, w, out, s);
+    case 84: return launch_rec<8, 4>(p, w, out, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s) {

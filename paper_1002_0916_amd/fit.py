@@ -41,7 +41,7 @@ def fit(x, y, z, a, target, nx: int, ny: int, iters: int = 100, lr: float = 1e-2
     opt = torch.optim.Adam([a_p, zp], lr=lr)
     losses = []
     if time_kernels:
-        for k in range(B.KERNEL_ADJ_SEPARABLE + 1):
+        for k in range(B.KERNEL_COUNT):
             B.profile_read(k)
         B.profile_enable(True)
     torch.cuda.synchronize()
@@ -66,9 +66,11 @@ def fit(x, y, z, a, target, nx: int, ny: int, iters: int = 100, lr: float = 1e-2
         v = B.variant_id(variant)
         sep = v in B.SEPARABLE_IDS
         fk = B.KERNEL_FWD_SEPARABLE if sep else {B.PLAIN: B.KERNEL_FWD_PLAIN,
-                                                 B.COMPENSATED: B.KERNEL_FWD_COMPENSATED}[v]
+                                                 B.COMPENSATED: B.KERNEL_FWD_COMPENSATED,
+                                                 B.RECURRENCE: B.KERNEL_FWD_RECURRENCE}[v]
         ak = B.KERNEL_ADJ_SEPARABLE if sep else {B.PLAIN: B.KERNEL_ADJ_PLAIN,
-                                                 B.COMPENSATED: B.KERNEL_ADJ_COMPENSATED}[v]
+                                                 B.COMPENSATED: B.KERNEL_ADJ_COMPENSATED,
+                                                 B.RECURRENCE: B.KERNEL_ADJ_PLAIN}[v]
         nf, tf = B.profile_read(fk)
         na, ta = B.profile_read(ak)
         res.fwd_ms = tf / max(nf, 1)

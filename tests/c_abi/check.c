@@ -6,9 +6,9 @@
  * (Section 1) then fixes I(x0, y0) = A (cos 0 = 1) and
  * I(x0 + u, y0 + v) = A cos(P (u^2 + v^2)), P = pi p^2 / (lambda z0); the
  * adjoint with G = 1 at pixel (x0 + u, y0 + v) and 0 elsewhere gives
- * dL/dA = cos(P (u^2 + v^2)).  Checked for the compensated and separable
- * variants; also the status codes of a bad call.  Prints "c abi ok" and
- * exits 0 on success.
+ * dL/dA = cos(P (u^2 + v^2)).  Checked for the compensated, separable
+ * (f16 hi/lo) and recurrence variants; also the status codes of a bad call.
+ * Prints "c abi ok" and exits 0 on success.
  */
 #include <math.h>
 #include <stdio.h>
@@ -102,9 +102,9 @@ static int run(int32_t variant) {
 }
 
 int main(void) {
-  if (cgh_version() < 101) return fail("version", cgh_version(), 101);
-  const int32_t variants[] = {CGH_COMPENSATED, CGH_SEPARABLE_F16X3};
-  for (int i = 0; i < 2; ++i) {
+  if (cgh_version() < 102) return fail("version", cgh_version(), 102);
+  const int32_t variants[] = {CGH_COMPENSATED, CGH_SEPARABLE_F16X3, CGH_RECURRENCE};
+  for (int i = 0; i < 3; ++i) {
     const int rc = run(variants[i]);
     if (rc) return rc;
   }

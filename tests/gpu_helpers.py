@@ -20,10 +20,12 @@ def _half_fwd_bar(u):
 
 # Acceptance bars for the forward, as fractions of sum_j |A_j|: max |dI| over
 # the compared pixels.
-TOL_FWD = {"plain": 2e-3, "compensated": 1e-4, "separable": 1e-4, "separable_f16x3": 1e-4,
+TOL_FWD = {"plain": 2e-3, "compensated": 1e-4, "recurrence": 2e-3, "separable": 1e-4,
+           "separable_f16x3": 1e-4,
            "separable_f16": _half_fwd_bar(U_F16), "separable_bf16": _half_fwd_bar(U_BF16)}
 # Relative L2 error bars per gradient group (A, x, y, z), same G on both sides.
-TOL_ADJ = {"plain": 1e-3, "compensated": 1e-4, "separable": 1e-4, "separable_f16x3": 1e-4,
+TOL_ADJ = {"plain": 1e-3, "compensated": 1e-4, "recurrence": 1e-3, "separable": 1e-4,
+           "separable_f16x3": 1e-4,
            "separable_f16": 2 * U_F16, "separable_bf16": 2 * U_BF16}
 
 

@@ -49,6 +49,25 @@ def test_binding_names_match_header():
     assert sorted(binding.EXPORTED) == declared_functions()
 
 
+def test_binding_constants_match_header():
+    """Every numeric #define of the header has the same value in the binding
+    (variants, operations, kernel ids, status codes)."""
+    from paper_1002_0916_amd import binding as B
+
+    with open(HEADER) as f:
+        defines = dict(re.findall(r"^#define (CGH_[A-Z0-9_]+) (\d+)", f.read(), flags=re.M))
+    checked = 0
+    for macro, value in defines.items():
+        # status codes keep their prefix in the binding, the rest drop it
+        status = macro == "CGH_OK" or macro.startswith("CGH_E")
+        attr = macro if status else macro[len("CGH_"):]
+        assert hasattr(B, attr), macro
+        assert getattr(B, attr) == int(value), macro
+        checked += 1
+    assert checked >= 20
+    assert max(B.VARIANTS.values()) == int(defines["CGH_RECURRENCE"])
+
+
 def test_strerror_and_version(lib):
     for code in range(4):
         assert isinstance(lib.cgh_strerror(code), bytes) and lib.cgh_strerror(code)
@@ -63,11 +82,12 @@ def test_workspace_bytes(lib):
     assert f(0, 16, 16, B.PLAIN, B.OP_FORWARD) == 0
     assert f(-1, 16, 16, B.PLAIN, B.OP_FORWARD) == 0
     assert f(10, 0, 16, B.PLAIN, B.OP_FORWARD) == 0
-    assert f(10, 16, 16, 7, B.OP_FORWARD) == 0
-    for v in B.SEPARABLE_IDS:
+    bad = max(B.VARIANTS.values()) + 1
+    assert f(10, 16, 16, bad, B.OP_FORWARD) == 0
+    assert f(10, 16, 16, -1, B.OP_FORWARD) == 0
+    for v in B.SEPARABLE_IDS + (B.RECURRENCE,):
         assert f(10, 16, 16, v, B.OP_FORWARD) > 0
         assert f(10, 16, 16, v, B.OP_BACKWARD) > 0
-    assert f(10, 16, 16, 6, B.OP_FORWARD) == 0
     assert f(10, 16, 16, B.PLAIN, 9) == 0
     assert f(4000001, 16, 16, B.PLAIN, B.OP_FORWARD) == 0
     assert f(4000000, 16, 16, B.PLAIN, B.OP_BACKWARD) > 0
@@ -111,7 +131,7 @@ def test_forward_rejects_bad_arguments(lib, case):
     elif case == "nan":
         args["pitch"] = float("nan")
     elif case == "variant":
-        args["v"] = 6
+        args["v"] = max(B.VARIANTS.values()) + 1
     elif case == "out":
         args["out"] = None
     elif case == "toolarge":
@@ -156,7 +176,8 @@ def test_backward_rejects_bad_arguments(lib):
         rc = lib.cgh_backward(p, p, p, p, 10, 32, 32, 8e-6, 633e-9, B.PLAIN, args["gh"],
                               args["gx"], args["gy"], args["gz"], args["ga"], p, 1 << 30, None)
         assert rc == B.CGH_EINVAL, k
-    rc = lib.cgh_backward(p, p, p, p, 10, 32, 32, 8e-6, 633e-9, 6, p, p, p, p, p, p, 1 << 30,
+    bad = max(B.VARIANTS.values()) + 1
+    rc = lib.cgh_backward(p, p, p, p, 10, 32, 32, 8e-6, 633e-9, bad, p, p, p, p, p, p, 1 << 30,
                           None)
     assert rc == B.CGH_EINVAL
     # n = 0 is a valid no-op that enqueues nothing
@@ -171,11 +192,11 @@ def test_profile_read_rejects_bad_kernel(lib):
     n = ctypes.c_int64(0)
     t = ctypes.c_double(0)
     assert lib.cgh_profile_read(-1, ctypes.byref(n), ctypes.byref(t)) == B.CGH_EINVAL
-    assert lib.cgh_profile_read(7, ctypes.byref(n), ctypes.byref(t)) == B.CGH_EINVAL
+    assert lib.cgh_profile_read(B.KERNEL_COUNT, ctypes.byref(n), ctypes.byref(t)) == B.CGH_EINVAL
     assert lib.cgh_profile_read(0, None, ctypes.byref(t)) == B.CGH_EINVAL
     buf = (ctypes.c_float * 4)()
     each = lib.cgh_profile_read_each
-    assert each(7, ctypes.byref(n), ctypes.byref(t), buf, 4) == B.CGH_EINVAL
+    assert each(B.KERNEL_COUNT, ctypes.byref(n), ctypes.byref(t), buf, 4) == B.CGH_EINVAL
     assert each(0, ctypes.byref(n), ctypes.byref(t), buf, -1) == B.CGH_EINVAL
     assert each(0, ctypes.byref(n), ctypes.byref(t), None, 4) == B.CGH_EINVAL
     # nothing recorded (timing is off): zero launches, nothing written

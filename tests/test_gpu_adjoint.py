@@ -15,8 +15,8 @@ from paper_1002_0916_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["plain", "compensated", "separable", "separable_f16x3", "separable_f16",
-            "separable_bf16"]
+VARIANTS = ["plain", "compensated", "recurrence", "separable", "separable_f16x3",
+            "separable_f16", "separable_bf16"]
 GROUPS = ("x", "y", "z", "a")
 
 

@@ -18,8 +18,8 @@ from paper_1002_0916_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["compensated", "plain", "separable", "separable_f16x3", "separable_f16",
-            "separable_bf16"]
+VARIANTS = ["compensated", "plain", "recurrence", "separable", "separable_f16x3",
+            "separable_f16", "separable_bf16"]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)

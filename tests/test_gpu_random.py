@@ -14,8 +14,8 @@ from paper_1002_0916_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["plain", "compensated", "separable", "separable_f16x3", "separable_f16",
-            "separable_bf16"]
+VARIANTS = ["plain", "compensated", "recurrence", "separable", "separable_f16x3",
+            "separable_f16", "separable_bf16"]
 
 CASES = dict(seed=st.integers(0, 2 ** 31 - 1), nx=st.integers(1, 260), ny=st.integers(1, 200),
              n=st.integers(1, 300), zlo=st.sampled_from([0.05, 0.2, 0.5, 2.0]),
