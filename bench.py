@@ -14,9 +14,10 @@ kernel (the adjoint) from HIP events recorded around it, accuracy against the
 FP64 GPU forward, and the FP64 CPU oracle's rate on a bounded sample of the
 same workload (the cpu_baseline leg, the only part that touches the oracle).
 Under "variants" the same step is reported for every variant (plain,
-compensated, the FP32 and 16-bit separable forms): step time eager and as a
-replayed HIP graph, mean / median / min kernel times, roofline fractions and
-the errors against FP64 (forward) and the compensated adjoint.
+compensated, the recurrence of Eq. (2), the FP32 and 16-bit separable forms):
+step time eager and as a replayed HIP graph, mean / median / min kernel
+times, roofline fractions and the errors against FP64 (forward) and the
+compensated adjoint.
 
 Other modes print one report line each: --workload (the other workload
 shapes, every variant, and the Adam fitting loop for fit4k), --sweep (the
