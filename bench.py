@@ -49,14 +49,15 @@ TRANS_SLOTS = 2
 #  adj compensated  X+Y add, sin, cos, Sc fma, column/row sums (2)    = 4 + 4
 #  fwd recurrence   Gamma += delta, cos, acc fma (delta += Delta is
 #                   shared by the rows of a lane; seeds are overhead) = 2 + 2
-# The recurrence variant's backward is the plain adjoint kernel.
+#  adj recurrence   Gamma += delta_c, sin, cos, Sc fma, column/row
+#                   sums (2) (delta_c kept per strip column)          = 4 + 4
 SLOTS = {
     "fwd_plain": 5 + TRANS_SLOTS,
     "fwd_compensated": 2 + TRANS_SLOTS,
     "fwd_recurrence": 2 + TRANS_SLOTS,
     "adj_plain": 6 + 2 * TRANS_SLOTS,
     "adj_compensated": 4 + 2 * TRANS_SLOTS,
-    "adj_recurrence": 6 + 2 * TRANS_SLOTS,
+    "adj_recurrence": 4 + 2 * TRANS_SLOTS,
 }
 # The same work if every packable FP32 add/mul/fma ran as packed math (two
 # lanes per slot; fract and the transcendentals do not pack).  Packed FP32 is
@@ -68,7 +69,7 @@ SLOTS_PACKED = {
     "fwd_recurrence": 2 / 2 + TRANS_SLOTS,
     "adj_plain": 5 / 2 + 1 + 2 * TRANS_SLOTS,
     "adj_compensated": 4 / 2 + 2 * TRANS_SLOTS,
-    "adj_recurrence": 5 / 2 + 1 + 2 * TRANS_SLOTS,
+    "adj_recurrence": 4 / 2 + 2 * TRANS_SLOTS,
 }
 # The separable variant is a different algorithm, bound by the FP32 matrix
 # cores (dense MFMA FP32 peak 157.3 TFLOP/s): the forward is one GEMM of
@@ -158,7 +159,7 @@ def measured_traffic(kernel):
 
 
 FWD_KERNEL = {"plain": 0, "compensated": 1, "recurrence": 7}
-ADJ_KERNEL = {"plain": 3, "compensated": 4, "recurrence": 3}
+ADJ_KERNEL = {"plain": 3, "compensated": 4, "recurrence": 8}
 for _v in MFMA_FLOPS:
     FWD_KERNEL[_v], ADJ_KERNEL[_v] = 5, 6
 

@@ -68,7 +68,8 @@
  *                       delta_{n-1}, delta_n = delta_{n-1} + Delta, each lane
  *                       producing a few consecutive pixels from the plain
  *                       FP32 phase Gamma_0 of the first (same accuracy class
- *                       as CGH_PLAIN).  Its backward is CGH_PLAIN's adjoint.
+ *                       as CGH_PLAIN).  Its backward steps the phase the same
+ *                       way along each 32-pixel run of a row.
  *    FP64 appears only in the per-point precompute of P_j / (2 pi) and its
  *    hi/lo split (and in cgh_forward_f64).
  */
@@ -111,7 +112,8 @@ extern "C" {
 #define CGH_KERNEL_FWD_SEPARABLE 5 /* the forward GEMM (every separable variant) */
 #define CGH_KERNEL_ADJ_SEPARABLE 6 /* both adjoint GEMMs, one event pair */
 #define CGH_KERNEL_FWD_RECURRENCE 7
-#define CGH_KERNEL_COUNT 8
+#define CGH_KERNEL_ADJ_RECURRENCE 8
+#define CGH_KERNEL_COUNT 9
 
 /*
  * Bytes of device workspace that `op` (CGH_OP_*) needs for n points on an

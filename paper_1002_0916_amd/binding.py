@@ -35,8 +35,8 @@ OP_FORWARD, OP_FORWARD_F64, OP_BACKWARD = 0, 1, 2
 KERNEL_FWD_PLAIN, KERNEL_FWD_COMPENSATED, KERNEL_FWD_F64 = 0, 1, 2
 KERNEL_ADJ_PLAIN, KERNEL_ADJ_COMPENSATED = 3, 4
 KERNEL_FWD_SEPARABLE, KERNEL_ADJ_SEPARABLE = 5, 6
-KERNEL_FWD_RECURRENCE = 7
-KERNEL_COUNT = 8
+KERNEL_FWD_RECURRENCE, KERNEL_ADJ_RECURRENCE = 7, 8
+KERNEL_COUNT = 9
 
 VARIANTS = {"plain": PLAIN, "fast": PLAIN, "compensated": COMPENSATED, "comp": COMPENSATED,
             "separable": SEPARABLE, "separable_f16x3": SEPARABLE_F16X3,

@@ -33,7 +33,13 @@ namespace cgh {
 
 namespace {
 
-template <int VARIANT>
+// KIND: kAdjPlain, kAdjCompensated or kAdjRecurrence.  With the recurrence
+// (Eq. (2), Section 2.1) each strip row starts from the plain phase
+// Gamma_0 = fract(Prev r^2) at the strip's first column and steps
+// Gamma += delta_c, delta_c = Prev (2 (x_c - x_j) + 1) reduced mod 1, the
+// same for every row (so the strip keeps delta_c where the plain path keeps
+// dx); |Gamma| stays below 1 + kAdjCols revolutions.
+template <int KIND>
 __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     const float4* __restrict__ plain, const float* __restrict__ xrec,
     const float* __restrict__ yrec, const float* __restrict__ g, int64_t ldg, int ny,
@@ -51,7 +57,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
   const float px = pr.x, py = pr.y, prev = pr.z;
   float xc = 0.f, xph = 0.f, xpl = 0.f, xb = 0.f, xd = 0.f;
   float yc = 0.f, yph = 0.f, ypl = 0.f, yb = 0.f, yd = 0.f;
-  if (VARIANT == 1) {
+  if (KIND == kAdjCompensated) {
     const float* rx = xrec + (int64_t)j * kAxisRec;
     xc = rx[0]; xph = rx[1]; xpl = rx[2]; xb = rx[3]; xd = rx[4];
     const float* ry = yrec + (int64_t)j * kAxisRec;
@@ -61,6 +67,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
   float Sc0 = 0.f, Sc1 = 0.f, Sx = 0.f, Sy = 0.f, Sr = 0.f;
   float CX[kAdjCols], SgC[kAdjCols];
   int col0 = 0, row1 = 0;
+  float dx0sq = 0.f;  // recurrence: (x_h - x_j)^2 at the strip's first column
 
   // G of one strip row lives in SGPRs.  Rows are software-pipelined with two
   // ping-pong buffers: the scalar loads of the next row are issued right
@@ -76,7 +83,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     const float yh = (float)row;
     const float dy = yh - py;
     const float dy2 = dy * dy;
-    const float RY = VARIANT == 1 ? axis_phase(yh, yc, yph, ypl, yb, yd) : dy2;
+    const float RY = KIND == kAdjCompensated ? axis_phase(yh, yc, yph, ypl, yb, yd) : dy2;
+    float gam = KIND == kAdjRecurrence ? fract(prev * (dx0sq + dy2)) : 0.f;
     float sr0 = 0.f, sr1 = 0.f;
 #pragma unroll
     for (int c = 0; c < kAdjCols; ++c) {
@@ -87,8 +95,11 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
       }
       const float G = gc[c];
       float t;
-      if (VARIANT == 1) {
+      if (KIND == kAdjCompensated) {
         t = CX[c] + RY;
+      } else if (KIND == kAdjRecurrence) {
+        t = gam;
+        gam += CX[c];
       } else {
         t = fract(prev * __builtin_fmaf(CX[c], CX[c], RY));
       }
@@ -114,12 +125,22 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     const int row0 = (int)(q - (int64_t)strip * ny);
     row1 = (int)min((int64_t)ny, row0 + (q1 - q));
     col0 = strip * kAdjCols;
-    // Column terms: the compensated x-phase of each strip column, or dx.
+    // Column terms: the compensated x-phase of each strip column, the
+    // recurrence step delta_c, or dx.
 #pragma unroll
     for (int c = 0; c < kAdjCols; ++c) {
       const float h = (float)(col0 + c);
-      CX[c] = VARIANT == 1 ? axis_phase(h, xc, xph, xpl, xb, xd) : h - px;
+      if (KIND == kAdjCompensated)
+        CX[c] = axis_phase(h, xc, xph, xpl, xb, xd);
+      else if (KIND == kAdjRecurrence)
+        CX[c] = fract(prev * __builtin_fmaf(2.0f, h - px, 1.0f));
+      else
+        CX[c] = h - px;
       SgC[c] = 0.f;
+    }
+    if (KIND == kAdjRecurrence) {
+      const float dx0 = (float)col0 - px;
+      dx0sq = dx0 * dx0;
     }
     float gA[kAdjCols], gB[kAdjCols];
     load_row(row0, gA);
@@ -204,7 +225,7 @@ hipError_t launch_pad_g(const Plan& p, const float* g, float* gpad, hipStream_t 
 }
 
 int adj_runs(const Plan& p) {
-  // Resident single-wave workgroups per CU of each variant, per device.
+  // Resident single-wave workgroups per CU of each adjoint kind, per device.
   static std::mutex mu;
   static std::map<std::pair<int, int>, int> cache;
   int dev = 0;
@@ -212,23 +233,27 @@ int adj_runs(const Plan& p) {
   int resident = 0;
   {
     std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find({dev, p.variant});
+    auto it = cache.find({dev, p.adj_kind});
     if (it != cache.end()) resident = it->second;
   }
   if (resident == 0) {
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return -1;
-    const hipError_t e =
-        p.variant == 1
-            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adj_partial_kernel<1>,
-                                                           kAdjThreads, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adj_partial_kernel<0>,
-                                                           kAdjThreads, 0);
+    hipError_t e;
+    if (p.adj_kind == kAdjCompensated)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, adj_partial_kernel<kAdjCompensated>, kAdjThreads, 0);
+    else if (p.adj_kind == kAdjRecurrence)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, adj_partial_kernel<kAdjRecurrence>, kAdjThreads, 0);
+    else
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, adj_partial_kernel<kAdjPlain>,
+                                                       kAdjThreads, 0);
     if (e != hipSuccess || cus < 1 || per_cu < 1) return -1;
     resident = cus * per_cu;
     std::lock_guard<std::mutex> lk(mu);
-    cache[{dev, p.variant}] = resident;
+    cache[{dev, p.adj_kind}] = resident;
   }
   int runs = (kAdjRounds * resident + p.ngroups - 1) / p.ngroups;
   if (runs > p.regions) runs = p.regions;
@@ -238,15 +263,17 @@ int adj_runs(const Plan& p) {
 hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* g, int64_t ldg,
                               int runs, hipStream_t s) {
   const dim3 grid(runs, p.ngroups);
-  if (p.variant == 1) {
-    hipLaunchKernelGGL(adj_partial_kernel<1>, grid, dim3(kAdjThreads), 0, s,
-                       (const float4*)w.plain, (const float*)w.xrec, (const float*)w.yrec, g, ldg,
-                       p.ny, p.strip_rows, (int)p.npad, (float4*)w.partial);
-  } else {
-    hipLaunchKernelGGL(adj_partial_kernel<0>, grid, dim3(kAdjThreads), 0, s,
-                       (const float4*)w.plain, (const float*)w.xrec, (const float*)w.yrec, g, ldg,
-                       p.ny, p.strip_rows, (int)p.npad, (float4*)w.partial);
-  }
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, grid, dim3(kAdjThreads), 0, s, (const float4*)w.plain,
+                       (const float*)w.xrec, (const float*)w.yrec, g, ldg, p.ny, p.strip_rows,
+                       (int)p.npad, (float4*)w.partial);
+  };
+  if (p.adj_kind == kAdjCompensated)
+    go(adj_partial_kernel<kAdjCompensated>);
+  else if (p.adj_kind == kAdjRecurrence)
+    go(adj_partial_kernel<kAdjRecurrence>);
+  else
+    go(adj_partial_kernel<kAdjPlain>);
   return hipGetLastError();
 }
 

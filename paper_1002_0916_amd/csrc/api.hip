@@ -116,6 +116,9 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   p.rec_gx = (int32_t)ceil_div(nx, (int64_t)kWave * p.rec_k);
   p.rec_gy = (int32_t)ceil_div(ny, (int64_t)kRecWaves * p.rec_r);
   p.ngroups = (int32_t)(p.npad / kWave);
+  p.adj_kind = variant == CGH_COMPENSATED  ? kAdjCompensated
+               : variant == CGH_RECURRENCE ? kAdjRecurrence
+                                           : kAdjPlain;
   p.nsx = (int32_t)ceil_div(nx, kAdjCols);
   p.strip_rows = (int64_t)p.nsx * ny;
   int64_t runs = ceil_div(kAdjMaxWaves, p.ngroups);
@@ -504,7 +507,9 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
   }
   const int runs = adj_runs(p);
   if (runs < 1) return CGH_EHIP;
-  const int kid = variant == CGH_COMPENSATED ? CGH_KERNEL_ADJ_COMPENSATED : CGH_KERNEL_ADJ_PLAIN;
+  const int kid = variant == CGH_COMPENSATED  ? CGH_KERNEL_ADJ_COMPENSATED
+                  : variant == CGH_RECURRENCE ? CGH_KERNEL_ADJ_RECURRENCE
+                                              : CGH_KERNEL_ADJ_PLAIN;
   const EventPair ev = profile_begin(kid, s);
   e = launch_adj_partial(p, w, g, ldg, runs, s);
   profile_end(kid, ev, s);

@@ -80,6 +80,12 @@ static_assert(kPointPad % (2 * kRecUnroll) == 0, "point padding holds whole grou
 // are split into equal contiguous runs, one per wave.  G is broadcast to the
 // wave through scalar loads, one strip row at a time.
 constexpr int kAdjCols = 32;
+// Phase arithmetic of the adjoint kernel (Plan::adj_kind): the plain FP32
+// phase, the compensated axis phases, or the recurrence of Eq. (2) along the
+// strip row.
+constexpr int kAdjPlain = 0;
+constexpr int kAdjCompensated = 1;
+constexpr int kAdjRecurrence = 2;
 constexpr int kAdjThreads = kWave;
 // At launch the number of runs is chosen so that kAdjRounds rounds of
 // resident waves (CUs x resident waves per CU, from the occupancy query)
@@ -148,7 +154,7 @@ struct Plan {
   int32_t rec_k, rec_r, rec_gx, rec_gy;  // recurrence forward shape and grid
   // adjoint: runs of strip-rows per point group (regions = the most runs the
   // partial buffer holds; the launch may use fewer)
-  int32_t nsx, regions, ngroups;
+  int32_t nsx, regions, ngroups, adj_kind;
   int64_t strip_rows;
   bool need_gpad;
   // separable variant

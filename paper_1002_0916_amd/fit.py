@@ -70,7 +70,7 @@ def fit(x, y, z, a, target, nx: int, ny: int, iters: int = 100, lr: float = 1e-2
                                                  B.RECURRENCE: B.KERNEL_FWD_RECURRENCE}[v]
         ak = B.KERNEL_ADJ_SEPARABLE if sep else {B.PLAIN: B.KERNEL_ADJ_PLAIN,
                                                  B.COMPENSATED: B.KERNEL_ADJ_COMPENSATED,
-                                                 B.RECURRENCE: B.KERNEL_ADJ_PLAIN}[v]
+                                                 B.RECURRENCE: B.KERNEL_ADJ_RECURRENCE}[v]
         nf, tf = B.profile_read(fk)
         na, ta = B.profile_read(ak)
         res.fwd_ms = tf / max(nf, 1)
