@@ -121,6 +121,9 @@ def parse():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the benchmark, run 5 plain device-to-device copies of this "
                          "many bytes (a known-traffic reference for hardware byte counters)")
+    ap.add_argument("--summarize", nargs=2, metavar=("KIND", "DIR"),
+                    help="no GPU: write the profiles/ summary of KIND (stats, traffic or "
+                         "counters) from the rocprofv3 CSV output under DIR")
     return ap.parse_args()
 
 
@@ -137,27 +140,25 @@ def copy_reference(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "copies": 5}), flush=True)
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, path=None):
     """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
     record (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy reference), or
     None when the kernel's sources have changed since the counters were taken."""
-    import hashlib
-
-    path = os.path.join(ROOT, "profiles", "traffic_paper_1920x1024_n1024.json")
+    if path is None:
+        path = os.path.join(ROOT, "profiles", "traffic_paper_1920x1024_n1024.json")
     try:
         with open(path) as f:
             rec = json.load(f)["kernels"][kernel]
     except (OSError, KeyError, ValueError):
         return None
-    h = hashlib.sha256()
-    for name in rec["sources"]:
-        with open(os.path.join(ROOT, "paper_1002_0916_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest()[:16] != rec["source_sha256_16"]:
+    if _sources_hash(rec["sources"]) != rec["source_sha256_16"]:
         return None
     return rec["traffic_bytes"]
 
 
+# Device-code names of the direct adjoint kernels (the roofline kernel).
+ADJ_KERNEL_NAME = {"plain": "adj_partial_kernel<0>", "compensated": "adj_partial_kernel<1>",
+                   "recurrence": "adj_partial_kernel<2>"}
 FWD_KERNEL = {"plain": 0, "compensated": 1, "recurrence": 7}
 ADJ_KERNEL = {"plain": 3, "compensated": 4, "recurrence": 8}
 for _v in MFMA_FLOPS:
@@ -220,6 +221,9 @@ def main():
               "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
+    if args.summarize:
+        summarize(*args.summarize)
+        return
     if args.copy_bytes > 0:
         copy_reference(args.copy_bytes)
         return
@@ -360,9 +364,8 @@ def main():
             "peak": peak,
             "unit": "Ginteraction/s",
             "frac": achieved / peak,
-            "traffic": (None if args.variant.startswith("separable") else
-                        measured_traffic("adj_partial_kernel<%d>"
-                                         % (1 if args.variant == "compensated" else 0))),
+            "traffic": (measured_traffic(ADJ_KERNEL_NAME[args.variant])
+                        if args.variant in ADJ_KERNEL_NAME else None),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                             "copy-calibrated)",
             "slots_per_interaction": SLOTS.get(adj_key),
@@ -684,6 +687,299 @@ def report_sweep(args):
             rec[variant + "_gpps"] = n * 1920 * 1024 / (ms * 1e-3) / 1e9
         rows.append(rec)
     print(json.dumps({"mode": "sweep", "hologram": "1920x1024", "rows": rows}), flush=True)
+
+
+# --------------------------------------------------------------------------
+# Summaries of rocprofv3 runs for profiles/ (no GPU needed: they read the CSV
+# files that the commands listed in each summary wrote).
+
+PROFILES = os.path.join(ROOT, "profiles")
+HEADLINE_INTERACTIONS = 1024 * 1920 * 1024
+_ROCPROF = "cd /tmp && export TMPDIR=/tmp && "
+
+
+def _kernel_short(name):
+    name = name.replace("void ", "").replace("cgh::(anonymous namespace)::", "")
+    name = name.replace("(anonymous namespace)::", "")
+    return name.split("(", 1)[0]
+
+
+def _csv_files(root, pattern):
+    import glob
+
+    files = sorted(glob.glob(os.path.join(root, "**", pattern), recursive=True))
+    if not files:
+        raise SystemExit("no %s under %s" % (pattern, root))
+    return files
+
+
+def _counter_means(files):
+    """{kernel: {counter: mean over dispatches}} from counter_collection CSVs."""
+    import collections
+    import csv
+
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for f in files:
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                acc[_kernel_short(r["Kernel_Name"])][r["Counter_Name"]].append(
+                    float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+
+
+def _write_md(name, lines):
+    path = os.path.join(PROFILES, name)
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", path)
+
+
+def summarize_stats(root):
+    """Kernel-duration table from `rocprofv3 --kernel-trace --stats` of the
+    default benchmark command."""
+    import csv
+
+    rows = []
+    for f in _csv_files(root, "*kernel_stats.csv"):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    cmd = (_ROCPROF + "timeout -s KILL 150 rocprofv3 --kernel-trace --stats -f csv -d <out>/stats "
+           "-o bench -- python3 bench.py --steps 10 --warmup 2 --no-cpu-baseline")
+    lines = ["# Kernel stats: bench.py step at 1920x1024, N=1024", "",
+             "Command (run from the repository root on the GPU box), then "
+             "`python bench.py --summarize stats <out>/stats`:", "", "```", cmd, "```", "",
+             "The run times every variant of the step (10 timed + 2 warm-up steps each, one "
+             "graph capture and 10 replays per variant, and the accuracy checks).  Kernel "
+             "names: fwd_comp_kernel / adj_partial_kernel<1> (compensated), fwd_plain_kernel / "
+             "adj_partial_kernel<0> (plain), fwd_rec_kernel<K, R> / adj_partial_kernel<2> "
+             "(recurrence), gemm_f32_kernel (separable FP32), gemm_half_kernel<format, fold> "
+             "(format 2 = fp16 hi/lo, 0 = fp16, 1 = bf16; fold 0 = forward, 1 and 2 = the "
+             "adjoint contractions).", "", "Durations in microseconds.", "",
+             "| kernel | calls | avg us | min us | max us | share |", "|---|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["Percentage"])):
+        lines.append("| %s | %s | %.1f | %.1f | %.1f | %.1f%% |" % (
+            _kernel_short(r["Name"])[:70], r["Calls"], float(r["AverageNs"]) / 1e3,
+            float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    # The JSON line that the profiled command printed (saved beside the CSVs
+    # as *.log): its HIP-event kernel means, taken in the same run.
+    line = None
+    for f in _csv_files(root, "*.log"):
+        with open(f) as fh:
+            for text in fh:
+                if text.startswith("{") and '"variants"' in text:
+                    line = json.loads(text)
+    if line is not None:
+        traced = {_kernel_short(r["Name"]): float(r["AverageNs"]) / 1e3 for r in rows}
+        pairs = [("fwd_comp_kernel", "compensated", "fwd"),
+                 ("adj_partial_kernel<1>", "compensated", "adj"),
+                 ("fwd_plain_kernel", "plain", "fwd"), ("adj_partial_kernel<0>", "plain", "adj"),
+                 ("fwd_rec_kernel<8, 4>", "recurrence", "fwd"),
+                 ("adj_partial_kernel<2>", "recurrence", "adj")]
+        lines += ["", "Agreement with the HIP events that bench.py records around the same kernels "
+                  "in the same profiled run (mean of the timed steps' launches; the trace "
+                  "average also covers warm-up, graph-replay and accuracy-check launches):", "",
+                  "| kernel | traced avg us | HIP-event mean us | traced / event |",
+                  "|---|---|---|---|"]
+        for k, v, op in pairs:
+            ev = line["variants"].get(v, {}).get(op + "_kernel_ms")
+            if k in traced and ev:
+                lines.append("| %s | %.1f | %.1f | %.3f |" % (k, traced[k], ev * 1e3,
+                                                              traced[k] / (ev * 1e3)))
+        lines += ["", "Profiled step of the headline (compensated) variant: %.3f ms." %
+                  line["ms_per_step"]]
+    _write_md("bench_paper_1920x1024_n1024_kernel_stats.md", lines)
+
+
+# Kernels whose traffic is recorded, with the sources their code comes from
+# (bench.py reports a kernel's traffic only while these hash the same) and
+# the algorithmic bytes of one launch at the headline workload.
+TRAFFIC_KERNELS = {
+    "adj_partial_kernel<1>": (["adjoint.hip", "phase.h", "cgh_internal.h"],
+                              "G 7.86 MB + records 0.08 MB + run partials 12.6 MB"),
+    "adj_partial_kernel<0>": (["adjoint.hip", "phase.h", "cgh_internal.h"], "same"),
+    "adj_partial_kernel<2>": (["adjoint.hip", "phase.h", "cgh_internal.h"], "same"),
+    "fwd_comp_kernel": (["forward.hip", "phase.h", "cgh_internal.h"],
+                        "row table 4.19 MB + records 0.05 MB + hologram 7.86 MB"),
+    "fwd_plain_kernel": (["forward.hip", "phase.h", "cgh_internal.h"],
+                         "records 0.02 MB + hologram 7.86 MB"),
+    "fwd_rec_kernel<8, 4>": (["forward.hip", "phase.h", "cgh_internal.h"],
+                             "records 0.02 MB + hologram 7.86 MB"),
+    "prep_kernel": (["prep.hip", "phase.h", "cgh_internal.h"],
+                    "inputs 0.02 MB + records 0.2 MB (+ f64 records)"),
+    "gemm_f32_kernel<true, true, 0>": (["gemm.hip", "fold.h", "phase.h", "cgh_internal.h"],
+                                       "tables 8.4 + 15.7 MB + split planes (forward)"),
+    "gemm_f32_kernel<false, false, 1>": (["gemm.hip", "fold.h", "phase.h", "cgh_internal.h"],
+                                         "tables 8.4 MB + G 7.86 MB + fold planes 0.5 MB"),
+    "gemm_f32_kernel<false, true, 2>": (["gemm.hip", "fold.h", "phase.h", "cgh_internal.h"],
+                                        "tables 15.7 MB + G 7.86 MB + fold planes 0.5 MB"),
+    "gemm_half_kernel<2, 0>": (["gemm_half.hip", "fold.h", "phase.h", "cgh_internal.h"],
+                               "hi+lo tables 12 MB + split planes (forward)"),
+    "gemm_half_kernel<2, 1>": (["gemm_half.hip", "fold.h", "phase.h", "cgh_internal.h"],
+                               "hi+lo tables 4.2 MB + hi+lo G 7.9 MB + fold planes 0.5 MB"),
+    "gemm_half_kernel<2, 2>": (["gemm_half.hip", "fold.h", "phase.h", "cgh_internal.h"],
+                               "hi+lo tables 7.9 MB + hi+lo G 7.9 MB + fold planes 0.5 MB"),
+    "gemm_half_kernel<0, 0>": (["gemm_half.hip", "fold.h", "phase.h", "cgh_internal.h"],
+                               "fp16 tables 6 MB + split planes (forward)"),
+    "sep_sum_slices_kernel": (["separable.hip", "phase.h", "cgh_internal.h"],
+                              "split planes + hologram 7.86 MB"),
+    "sep_adj_operands_half_kernel<2>": (["separable_half.hip", "phase.h", "cgh_internal.h"],
+                                        "G 7.86 MB in; G, Gt, Xt, Yt hi+lo planes 41 MB out"),
+}
+
+
+def _sources_hash(sources):
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in sources:
+        with open(os.path.join(ROOT, "paper_1002_0916_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def summarize_traffic(root):
+    """HBM bytes per launch from FETCH_SIZE and WRITE_SIZE runs of the benchmark,
+    scaled by what the same counters read for a plain copy of known size."""
+    copy_bytes = 268435456
+    fe = _counter_means(_csv_files(os.path.join(root, "fetch"), "*counter_collection.csv"))
+    wr = _counter_means(_csv_files(os.path.join(root, "write"), "*counter_collection.csv"))
+    cf = _counter_means(_csv_files(os.path.join(root, "copy_fetch"), "*counter_collection.csv"))
+    cw = _counter_means(_csv_files(os.path.join(root, "copy_write"), "*counter_collection.csv"))
+    copy_f = cf["__amd_rocclr_copyBuffer"]["FETCH_SIZE"]
+    copy_w = cw["__amd_rocclr_copyBuffer"]["WRITE_SIZE"]
+    ff, wf = copy_f * 1024 / copy_bytes, copy_w * 1024 / copy_bytes
+    kernels = {}
+    for k, (sources, _) in TRAFFIC_KERNELS.items():
+        if k not in fe or k not in wr:
+            print("no counters for", k)
+            continue
+        f_raw, w_raw = fe[k]["FETCH_SIZE"], wr[k]["WRITE_SIZE"]
+        kernels[k] = {"fetch_kib_raw": round(f_raw, 1), "write_kib_raw": round(w_raw, 1),
+                      "fetch_bytes": f_raw * 1024 / ff, "write_bytes": w_raw * 1024 / wf,
+                      "traffic_bytes": f_raw * 1024 / ff + w_raw * 1024 / wf,
+                      "source_sha256_16": _sources_hash(sources), "sources": sources}
+    rec = {"workload": "1920x1024 hologram, N=1024 points (bench.py step)",
+           "copy_reference_bytes": copy_bytes, "fetch_factor": ff, "write_factor": wf,
+           "kernels": kernels}
+    with open(os.path.join(PROFILES, "traffic_paper_1920x1024_n1024.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    runs = [("fetch", "FETCH_SIZE", "bench.py --steps 3 --warmup 1 --no-cpu-baseline"),
+            ("write", "WRITE_SIZE", "bench.py --steps 3 --warmup 1 --no-cpu-baseline"),
+            ("copy_fetch", "FETCH_SIZE", "bench.py --copy-bytes %d" % copy_bytes),
+            ("copy_write", "WRITE_SIZE", "bench.py --copy-bytes %d" % copy_bytes)]
+    lines = ["# HBM traffic per launch: bench.py step at 1920x1024, N=1024", "",
+             "Commands (from the repository root on the GPU box, one counter per run), then "
+             "`python bench.py --summarize traffic <out>`:", "", "```", _ROCPROF.rstrip(" &")]
+    for d, counter, cmd in runs:
+        lines.append("timeout -s KILL 150 rocprofv3 --kernel-trace --pmc %s -f csv -d <out>/%s "
+                     "-o %s -- python3 %s" % (counter, d, d, cmd))
+    lines += ["```", "",
+              "Calibration: a plain %d-byte device copy (`__amd_rocclr_copyBuffer`, reads and "
+              "writes that many bytes) reads FETCH_SIZE = %.0f KiB and WRITE_SIZE = %.0f KiB per "
+              "dispatch, so bytes = FETCH_SIZE x 1024 / %.5f and WRITE_SIZE x 1024 / %.3f."
+              % (copy_bytes, copy_f, copy_w, ff, wf), "",
+              "Counter values are averages over the kernel's dispatches in the run (every "
+              "variant of the step).  `traffic_paper_1920x1024_n1024.json` holds the same "
+              "figures with a hash of each kernel's sources; bench.py reports the traffic of "
+              "the roofline kernel only while that hash matches.", "",
+              "| kernel | FETCH_SIZE KiB (raw) | WRITE_SIZE KiB (raw) | fetch | write | total | "
+              "algorithmic bytes |", "|---|---|---|---|---|---|---|"]
+    for k, v in kernels.items():
+        lines.append("| %s | %.0f | %.0f | %.2f MB | %.2f MB | %.2f MB | %s |" % (
+            k, v["fetch_kib_raw"], v["write_kib_raw"], v["fetch_bytes"] / 1e6,
+            v["write_bytes"] / 1e6, v["traffic_bytes"] / 1e6, TRAFFIC_KERNELS[k][1]))
+    _write_md("traffic_paper_1920x1024_n1024.md", lines)
+
+
+COUNTER_PASSES = (
+    "SQ_INSTS_VALU SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_SALU SQ_INSTS_SMEM SQ_INSTS_LDS SQ_WAVES "
+    "GRBM_GUI_ACTIVE",
+    "SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_MFMA SQ_VALU_MFMA_BUSY_CYCLES "
+    "GRBM_GUI_ACTIVE GRBM_COUNT",
+)
+# Direct kernels per variant, with the algorithmic (instructions, of which
+# transcendental, issue slots) per interaction.
+COUNTER_KERNELS = {
+    "compensated": {"fwd_comp_kernel": (3, 1, 4), "adj_partial_kernel<1>": (6, 2, 8)},
+    "plain": {"fwd_plain_kernel": (6, 1, 7), "adj_partial_kernel<0>": (8, 2, 10)},
+    "recurrence": {"fwd_rec_kernel<8, 4>": (3, 1, 4), "adj_partial_kernel<2>": (6, 2, 8)},
+}
+
+
+def summarize_counters(root):
+    """Per-interaction VALU, transcendental, SALU, SMEM and LDS instruction
+    counts and VALU busy of the direct kernels, and matrix-core use of the
+    fp16 hi/lo GEMM, from two counter passes per variant (DIR/<variant>.<pass>)."""
+    variants = list(COUNTER_KERNELS) + ["separable_f16x3"]
+    data = {}
+    for v in variants:
+        files = [f for p in (1, 2)
+                 for f in _csv_files(os.path.join(root, "%s.%d" % (v, p)), "*counter_collection.csv")]
+        data[v] = _counter_means(files)
+    # The fp16 hi/lo GEMM runs as three instantiations per step (forward and
+    # the two adjoint contractions, one dispatch each): average them.
+    half = [c for k, c in data["separable_f16x3"].items() if k.startswith("gemm_half_kernel<2,")]
+    if half:
+        data["separable_f16x3"]["gemm_half_kernel<2>"] = {
+            name: sum(c[name] for c in half) / len(half) for name in half[0]}
+    n = HEADLINE_INTERACTIONS
+    lines = ["# Hardware counters of the hot kernels, 1920x1024 hologram, N = 1024", "",
+             "Two counter passes per variant (rocprofv3 does not split counters over passes), "
+             "from the repository root on the GPU box, then `python bench.py --summarize "
+             "counters <out>`:", "", "```", _ROCPROF.rstrip(" &")]
+    for v in variants:
+        for i, counters in enumerate(COUNTER_PASSES, 1):
+            lines.append("timeout -s KILL 90 rocprofv3 --pmc %s -f csv -d <out>/%s.%d -o pmc -- "
+                         "python3 bench.py --variant %s --only --steps 5 --warmup 1 "
+                         "--no-cpu-baseline" % (counters, v, i, v))
+    lines += ["```", "",
+              "Counter values are averages over the kernel's dispatches.  SQ_INSTS_* count wave "
+              "instructions (64 lanes each) over the chip; GRBM_GUI_ACTIVE is summed over the 8 "
+              "XCDs; VALU busy is 4 SQ_ACTIVE_INST_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE / 8).", "",
+              "Per point-pixel interaction (N nx ny = %d; lanes that compute padding count):" % n,
+              "", "| kernel | VALU instr | of which transcendental | algorithmic instr (slots) | "
+              "issued slots (trans = 2) | VALU busy | SALU / VALU | SMEM / VALU | LDS / VALU |",
+              "|---|---|---|---|---|---|---|---|---|"]
+    for v, ks in COUNTER_KERNELS.items():
+        for k, (ins, _, slots) in ks.items():
+            c = data[v].get(k)
+            if c is None:
+                print("no counters for", k)
+                continue
+            valu = c["SQ_INSTS_VALU"] * 64 / n
+            tr = c["SQ_INSTS_VALU_TRANS_F32"] * 64 / n
+            busy = 4 * c["SQ_ACTIVE_INST_VALU"] / (1024 * c["GRBM_GUI_ACTIVE"] / 8)
+            lines.append("| `%s` | %.2f | %.2f | %d (%d) | %.2f | %.0f%% | %.3f | %.4f | %.4f |" % (
+                k, valu, tr, ins, slots, valu + tr, 100 * busy,
+                c["SQ_INSTS_SALU"] / c["SQ_INSTS_VALU"], c["SQ_INSTS_SMEM"] / c["SQ_INSTS_VALU"],
+                c["SQ_INSTS_LDS"] / c["SQ_INSTS_VALU"]))
+    g = data["separable_f16x3"].get("gemm_half_kernel<2>")
+    if g is not None:
+        mf = g["SQ_VALU_MFMA_BUSY_CYCLES"] / (1024 * g["GRBM_GUI_ACTIVE"] / 8)
+        lines += ["", "Matrix-core kernel (`gemm_half_kernel<2>`, the fp16 hi/lo GEMM of the "
+                  "separable_f16x3 variant; average over its forward and two adjoint dispatches "
+                  "per step):", "",
+                  "| MFMA instr / dispatch | MFMA busy cycles / MFMA | MFMA busy | LDS instr / MFMA "
+                  "| VALU instr / MFMA |", "|---|---|---|---|---|",
+                  "| %.0f | %.1f | %.0f%% | %.2f | %.2f |" % (
+                      g["SQ_INSTS_MFMA"], g["SQ_VALU_MFMA_BUSY_CYCLES"] / g["SQ_INSTS_MFMA"],
+                      100 * mf, g["SQ_INSTS_LDS"] / g["SQ_INSTS_MFMA"],
+                      g["SQ_INSTS_VALU"] / g["SQ_INSTS_MFMA"])]
+    lines += ["", "Raw averages per dispatch:", "", "| kernel | counter | value |", "|---|---|---|"]
+    for v in variants:
+        ks = list(COUNTER_KERNELS.get(v, {})) or ["gemm_half_kernel<2>"]
+        for k in ks:
+            for name, val in sorted(data[v].get(k, {}).items()):
+                lines.append("| `%s` | %s | %.6g |" % (k, name, val))
+    _write_md("counters_paper_1920x1024_n1024.md", lines)
+
+
+def summarize(kind, root):
+    fn = {"stats": summarize_stats, "traffic": summarize_traffic,
+          "counters": summarize_counters}.get(kind)
+    if fn is None:
+        raise SystemExit("--summarize KIND must be stats, traffic or counters")
+    fn(root)
 
 
 def _cpu_model():

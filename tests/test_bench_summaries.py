@@ -1,0 +1,123 @@
+"""The profiles/ summaries that bench.py writes from rocprofv3 CSV output
+(`bench.py --summarize`), on small synthetic CSV files: the copy calibration
+of FETCH_SIZE / WRITE_SIZE, the per-interaction counter arithmetic, the
+trace-versus-event table, and the rule that a kernel's recorded traffic is
+withheld once its sources change.  No GPU."""
+import csv
+import importlib.util
+import json
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+HEADER = ["Correlation_Id", "Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name",
+          "Counter_Value"]
+ADJ1 = ("void cgh::(anonymous namespace)::adj_partial_kernel<1>(HIP_vector_type<float, 4u> "
+        "const*, float const*, long, int)")
+
+
+@pytest.fixture()
+def bench(tmp_path, monkeypatch):
+    spec = importlib.util.spec_from_file_location("bench_under_test",
+                                                  os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    out = tmp_path / "profiles"
+    out.mkdir()
+    monkeypatch.setattr(mod, "PROFILES", str(out))
+    return mod
+
+
+def _counters(path, rows):
+    path.parent.mkdir(parents=True, exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f, quoting=csv.QUOTE_NONNUMERIC)
+        w.writerow(HEADER)
+        for i, (kernel, counter, value) in enumerate(rows):
+            w.writerow([i + 1, i + 1, kernel, 1024, counter, float(value)])
+
+
+def test_traffic_is_copy_calibrated_and_withheld_when_sources_change(bench, tmp_path):
+    run = tmp_path / "run"
+    # the kernel: FETCH_SIZE 1000 and 3000 KiB (mean 2000), WRITE_SIZE 500 KiB
+    _counters(run / "fetch" / "f_counter_collection.csv",
+              [(ADJ1, "FETCH_SIZE", 1000), (ADJ1, "FETCH_SIZE", 3000)])
+    _counters(run / "write" / "w_counter_collection.csv", [(ADJ1, "WRITE_SIZE", 500)])
+    # a 256 MiB copy reads FETCH_SIZE = half its bytes and WRITE_SIZE = all of them
+    _counters(run / "copy_fetch" / "c_counter_collection.csv",
+              [("__amd_rocclr_copyBuffer", "FETCH_SIZE", 131072)] * 2)
+    _counters(run / "copy_write" / "c_counter_collection.csv",
+              [("__amd_rocclr_copyBuffer", "WRITE_SIZE", 262144)])
+    bench.summarize("traffic", str(run))
+    path = os.path.join(bench.PROFILES, "traffic_paper_1920x1024_n1024.json")
+    with open(path) as f:
+        rec = json.load(f)
+    assert rec["fetch_factor"] == pytest.approx(0.5)
+    assert rec["write_factor"] == pytest.approx(1.0)
+    k = rec["kernels"]["adj_partial_kernel<1>"]
+    assert k["fetch_bytes"] == pytest.approx(2000 * 1024 / 0.5)
+    assert k["write_bytes"] == pytest.approx(500 * 1024)
+    assert bench.measured_traffic("adj_partial_kernel<1>", path) == pytest.approx(
+        2000 * 1024 / 0.5 + 500 * 1024)
+    assert os.path.exists(os.path.join(bench.PROFILES, "traffic_paper_1920x1024_n1024.md"))
+    # a kernel without counters is left out; a changed source withholds the figure
+    assert bench.measured_traffic("adj_partial_kernel<0>", path) is None
+    k["source_sha256_16"] = "0" * 16
+    with open(path, "w") as f:
+        json.dump(rec, f)
+    assert bench.measured_traffic("adj_partial_kernel<1>", path) is None
+
+
+def test_counter_summary_per_interaction(bench, tmp_path):
+    run = tmp_path / "ctr"
+    n = bench.HEADLINE_INTERACTIONS
+    gui = 8 * 2.4e3 * 100  # 100 us of 8 XCDs' GRBM_GUI_ACTIVE at 2.4 GHz
+    for v, kernels in bench.COUNTER_KERNELS.items():
+        for i, k in enumerate(kernels):
+            name = "void cgh::(anonymous namespace)::%s(float const*)" % k
+            _counters(run / ("%s.1" % v) / ("k%d_counter_collection.csv" % i),
+                      [(name, "SQ_INSTS_VALU", 4 * n / 64), (name, "SQ_INSTS_VALU_TRANS_F32", n / 64),
+                       (name, "SQ_INSTS_SALU", n / 64), (name, "SQ_INSTS_SMEM", n / 640),
+                       (name, "SQ_INSTS_LDS", 0), (name, "SQ_WAVES", 1), (name, "GRBM_GUI_ACTIVE", gui)])
+            _counters(run / ("%s.2" % v) / ("k%d_counter_collection.csv" % i),
+                      [(name, "SQ_ACTIVE_INST_VALU", 0.5 * 1024 * gui / 8 / 4),
+                       (name, "GRBM_GUI_ACTIVE", gui)])
+    g = "void cgh::(anonymous namespace)::gemm_half_kernel<2, 0>(float const*)"
+    _counters(run / "separable_f16x3.1" / "x_counter_collection.csv",
+              [(g, "SQ_INSTS_VALU", 300), (g, "SQ_INSTS_LDS", 100), (g, "GRBM_GUI_ACTIVE", gui)])
+    _counters(run / "separable_f16x3.2" / "x_counter_collection.csv",
+              [(g, "SQ_INSTS_MFMA", 100), (g, "SQ_VALU_MFMA_BUSY_CYCLES", 3200),
+               (g, "GRBM_GUI_ACTIVE", gui)])
+    bench.summarize("counters", str(run))
+    with open(os.path.join(bench.PROFILES, "counters_paper_1920x1024_n1024.md")) as f:
+        text = f.read()
+    # 4 VALU and 1 transcendental per interaction: 5 issued slots; VALU busy 50%
+    assert "| `fwd_comp_kernel` | 4.00 | 1.00 | 3 (4) | 5.00 | 50% | 0.250 | 0.0250 | 0.0000 |" in text
+    assert "| `adj_partial_kernel<2>` | 4.00 | 1.00 | 6 (8) | 5.00 | 50% |" in text
+    assert "| 100 | 32.0 |" in text  # MFMA per dispatch, busy cycles per MFMA
+
+
+def test_stats_summary_compares_trace_with_events(bench, tmp_path):
+    run = tmp_path / "stats"
+    run.mkdir()
+    with open(run / "bench_kernel_stats.csv", "w", newline="") as f:
+        w = csv.writer(f, quoting=csv.QUOTE_NONNUMERIC)
+        w.writerow(["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs",
+                    "MaxNs", "StdDev"])
+        w.writerow([ADJ1, 10, 4.6e6, 460000.0, 60.0, 450000, 470000, 1.0])
+    line = {"ms_per_step": 0.7, "variants": {"compensated": {"adj_kernel_ms": 0.46,
+                                                             "fwd_kernel_ms": 0.25}}}
+    with open(run / "bench_stdout.log", "w") as f:
+        f.write("noise\n" + json.dumps(line) + "\n")
+    bench.summarize("stats", str(run))
+    with open(os.path.join(bench.PROFILES, "bench_paper_1920x1024_n1024_kernel_stats.md")) as f:
+        text = f.read()
+    assert "| adj_partial_kernel<1> | 10 | 460.0 | 450.0 | 470.0 | 60.0% |" in text
+    assert "| adj_partial_kernel<1> | 460.0 | 460.0 | 1.000 |" in text
+
+
+def test_summarize_rejects_unknown_kind(bench):
+    with pytest.raises(SystemExit):
+        bench.summarize("nonsense", "/nonexistent")
