@@ -827,13 +827,25 @@ TRAFFIC_KERNELS = {
 }
 
 
-def _sources_hash(sources):
+def _code_text(text):
+    """Source text without comments and with whitespace collapsed, so that a
+    comment edit leaves a kernel's recorded traffic valid and a code edit
+    does not."""
+    import re
+
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def _sources_hash(sources, base=None):
     import hashlib
 
+    base = base or os.path.join(ROOT, "paper_1002_0916_amd", "csrc")
     h = hashlib.sha256()
     for name in sources:
-        with open(os.path.join(ROOT, "paper_1002_0916_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(base, name)) as f:
+            h.update(_code_text(f.read()).encode())
     return h.hexdigest()[:16]
 
 

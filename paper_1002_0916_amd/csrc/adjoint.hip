@@ -9,12 +9,13 @@
 // four per-point reductions over pixels runs inside one lane and no
 // cross-lane reduction is needed at all.  A wave takes 64 points and an equal
 // share (a run) of the strip-rows of the hologram, where a strip is kAdjCols
-// columns wide; one round of resident waves covers everything.  G is
+// columns wide; kAdjRounds rounds of resident waves cover everything.  G is
 // wave-uniform and reaches the lanes through scalar loads, one strip row
 // (kAdjCols floats) at a time.  The pixel-dependent factors separate by axis,
-// r^2 = dx^2 + dy^2, so per strip the lane keeps the column phases (or dx) and
-// the column sums of G sin(theta) in registers, and per row it forms the row
-// phase (or dy^2) once and folds the row sum of G sin(theta) with dy and dy^2.
+// r^2 = dx^2 + dy^2, so per strip the lane keeps the column phases (or dx, or
+// the recurrence steps) and the column sums of G sin(theta) in registers, and
+// per row it forms the row phase (or dy^2) once and folds the row sum of
+// G sin(theta) with dy and dy^2.
 // Per interaction that leaves the phase, sin and cos, and three fused
 // multiply-adds with G taken straight from an SGPR.
 //

@@ -25,9 +25,10 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned i, unsigned n) {
 }
 
 // ---------------------------------------------------------------- forward --
-// A forward workgroup is 4 waves.  Lane l of every wave owns hologram column
-// x0 + l; wave w owns kRows consecutive rows, so a workgroup covers 64 columns
-// x (4 * kRows) rows and every lane produces kRows pixels of one column.
+// Plain forward: a workgroup is 4 waves.  Lane l of every wave owns hologram
+// column x0 + l; wave w owns kRows consecutive rows, so a workgroup covers 64
+// columns x (4 * kRows) rows and every lane produces kRows pixels of one
+// column.
 constexpr int kFwdWaves = 4;
 constexpr int kRows = 8;
 constexpr int kFwdThreads = kFwdWaves * kWave;

@@ -1,12 +1,14 @@
 // Forward kernels: the direct point-source sum of Eq. (1) (Section 1).
 //
-// Work mapping (all three kernels): one hologram pixel per lane.  The FP32
-// kernels give lane l of a wave column x0 + l and kRows consecutive rows, so a
-// wave writes kRows fully coalesced 256-byte row segments, and every point
-// record is read once per wave through scalar loads (the loop index is
+// Work mapping: one hologram column per lane.  The plain and compensated FP32
+// kernels give lane l of a wave column x0 + l and a few consecutive rows, so a
+// wave writes fully coalesced 256-byte row segments, and every point record
+// is read once per wave through scalar loads (the loop index is
 // wave-uniform), i.e. broadcast to all 64 lanes from SGPRs.  Points are
-// unrolled kUnroll at a time so the scalar loads of the next points are in
-// flight while the current ones are used.
+// unrolled a group at a time so the scalar loads of the next points are in
+// flight while the current ones are used.  The recurrence kernel gives a lane
+// K consecutive columns of R rows instead (Eq. (2) steps along x), and the
+// FP64 reference one pixel per lane.
 #include "cgh_internal.h"
 #include "phase.h"
 

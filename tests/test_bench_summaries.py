@@ -121,3 +121,13 @@ def test_stats_summary_compares_trace_with_events(bench, tmp_path):
 def test_summarize_rejects_unknown_kind(bench):
     with pytest.raises(SystemExit):
         bench.summarize("nonsense", "/nonexistent")
+
+
+def test_source_hash_ignores_comments_not_code(bench, tmp_path):
+    src = "__global__ void k(float* p) {\n  p[0] = 1.0f;  // one\n}\n"
+    (tmp_path / "k.hip").write_text(src)
+    h = bench._sources_hash(["k.hip"], str(tmp_path))
+    (tmp_path / "k.hip").write_text("/* a new\n   comment */\n" + src.replace("// one", "// uno"))
+    assert bench._sources_hash(["k.hip"], str(tmp_path)) == h
+    (tmp_path / "k.hip").write_text(src.replace("1.0f", "2.0f"))
+    assert bench._sources_hash(["k.hip"], str(tmp_path)) != h
