@@ -203,8 +203,8 @@ def backward(x, y, z, a, grad, nx: int, ny: int, pitch: float = 8e-6,
     nx, ny = _sizes(nx, ny)
     v = variant_id(variant)
     if (not isinstance(grad, torch.Tensor) or grad.dtype != torch.float32
-            or grad.device != dev or grad.numel() != nx * ny):
-        raise ValueError("grad must be a float32 tensor of ny*nx on x's device")
+            or grad.device != dev or tuple(grad.shape) != (ny, nx)):
+        raise ValueError("grad must be a float32 tensor of shape (ny, nx) on x's device")
     grad = grad.contiguous()
     gx, gy, gz, ga = (torch.empty(n, dtype=torch.float32, device=dev) for _ in range(4))
     stream = torch.cuda.current_stream(dev)

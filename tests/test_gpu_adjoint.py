@@ -93,6 +93,19 @@ def test_deterministic(oracle_mod, variant):
         assert np.array_equal(u, v)
 
 
+def test_backward_rejects_misshaped_grad():
+    """G is [ny][nx]: a transposed or flat tensor of the same size is refused
+    rather than read in the wrong layout."""
+    dev = device()
+    x, y, z, a = to_dev(W.random_cloud(7, 10, 40, 30), dev)
+    for shape in [(40, 30), (1200,), (1, 30, 40)]:
+        with pytest.raises(ValueError):
+            B.backward(x, y, z, a, torch.zeros(shape, device=dev), 40, 30)
+    out = B.backward(x, y, z, a, torch.zeros((30, 40), device=dev), 40, 30)
+    torch.cuda.synchronize()
+    assert all(t.numel() == 10 for t in out)
+
+
 def test_empty_point_set():
     dev = device()
     e = torch.zeros(0, dtype=torch.float32, device=dev)
