@@ -217,7 +217,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: no multi-GPU path is implemented "
               "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
@@ -746,7 +746,7 @@ def summarize_stats(root):
     cmd = (_ROCPROF + "timeout -s KILL 150 rocprofv3 --kernel-trace --stats -f csv -d <out>/stats "
            "-o bench -- python3 bench.py --steps 10 --warmup 2 --no-cpu-baseline")
     lines = ["# Kernel stats: bench.py step at 1920x1024, N=1024", "",
-             "Command (run from the repository root on the GPU box), then "
+             "Command (run from the repository root on an MI355X machine), then "
              "`python bench.py --summarize stats <out>/stats`:", "", "```", cmd, "```", "",
              "The run times every variant of the step (10 timed + 2 warm-up steps each, one "
              "graph capture and 10 replays per variant, and the accuracy checks).  Kernel "
@@ -880,7 +880,7 @@ def summarize_traffic(root):
             ("copy_fetch", "FETCH_SIZE", "bench.py --copy-bytes %d" % copy_bytes),
             ("copy_write", "WRITE_SIZE", "bench.py --copy-bytes %d" % copy_bytes)]
     lines = ["# HBM traffic per launch: bench.py step at 1920x1024, N=1024", "",
-             "Commands (from the repository root on the GPU box, one counter per run), then "
+             "Commands (from the repository root on an MI355X machine, one counter per run), then "
              "`python bench.py --summarize traffic <out>`:", "", "```", _ROCPROF.rstrip(" &")]
     for d, counter, cmd in runs:
         lines.append("timeout -s KILL 150 rocprofv3 --kernel-trace --pmc %s -f csv -d <out>/%s "
@@ -937,7 +937,7 @@ def summarize_counters(root):
     n = HEADLINE_INTERACTIONS
     lines = ["# Hardware counters of the hot kernels, 1920x1024 hologram, N = 1024", "",
              "Two counter passes per variant (rocprofv3 does not split counters over passes), "
-             "from the repository root on the GPU box, then `python bench.py --summarize "
+             "from the repository root on an MI355X machine, then `python bench.py --summarize "
              "counters <out>`:", "", "```", _ROCPROF.rstrip(" &")]
     for v in variants:
         for i, counters in enumerate(COUNTER_PASSES, 1):
