@@ -29,6 +29,7 @@
 
 #include "cgh_internal.h"
 #include "phase.h"
+#include "records.h"
 
 namespace cgh {
 
@@ -42,9 +43,10 @@ namespace {
 // dx); |Gamma| stays below 1 + kAdjCols revolutions.
 template <int KIND>
 __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
-    const float4* __restrict__ plain, const float* __restrict__ xrec,
-    const float* __restrict__ yrec, const float* __restrict__ g, int64_t ldg, int ny,
-    int64_t strip_rows, int npad, float4* __restrict__ partial) {
+    const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
+    const float* __restrict__ a, int64_t n, double pitch, double wavelength,
+    const float* __restrict__ g, int64_t ldg, int ny, int64_t strip_rows, int npad,
+    float4* __restrict__ partial) {
   // Neighbouring runs and all point groups of a run share G: keep them on
   // one XCD.
   const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
@@ -54,16 +56,11 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
   const int64_t q0 = strip_rows * run / runs;
   const int64_t q1 = strip_rows * (run + 1) / runs;
 
-  const float4 pr = plain[j];
-  const float px = pr.x, py = pr.y, prev = pr.z;
-  float xc = 0.f, xph = 0.f, xpl = 0.f, xb = 0.f, xd = 0.f;
-  float yc = 0.f, yph = 0.f, ypl = 0.f, yb = 0.f, yd = 0.f;
-  if (KIND == kAdjCompensated) {
-    const float* rx = xrec + (int64_t)j * kAxisRec;
-    xc = rx[0]; xph = rx[1]; xpl = rx[2]; xb = rx[3]; xd = rx[4];
-    const float* ry = yrec + (int64_t)j * kAxisRec;
-    yc = ry[0]; yph = ry[1]; ypl = ry[2]; yb = ry[3]; yd = ry[4];
-  }
+  // This lane's point (j >= n: a zero-amplitude padding point).
+  const PointRecord rec = point_record(x, y, z, a, j, n, pitch, wavelength);
+  const float px = rec.x, py = rec.y, prev = rec.ph;
+  const float xc = rec.xc, xph = rec.ph, xpl = rec.pl, xb = rec.xb, xd = rec.xd;
+  const float yc = rec.yc, yph = rec.ph, ypl = rec.pl, yb = rec.yb, yd = rec.yd;
 
   float Sc0 = 0.f, Sc1 = 0.f, Sx = 0.f, Sy = 0.f, Sr = 0.f;
   float CX[kAdjCols], SgC[kAdjCols];
@@ -261,13 +258,13 @@ int adj_runs(const Plan& p) {
   return runs < 1 ? 1 : runs;
 }
 
-hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* g, int64_t ldg,
-                              int runs, hipStream_t s) {
+hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* x, const float* y,
+                              const float* z, const float* a, double pitch, double wavelength,
+                              const float* g, int64_t ldg, int runs, hipStream_t s) {
   const dim3 grid(runs, p.ngroups);
   auto go = [&](auto kernel) {
-    hipLaunchKernelGGL(kernel, grid, dim3(kAdjThreads), 0, s, (const float4*)w.plain,
-                       (const float*)w.xrec, (const float*)w.yrec, g, ldg, p.ny, p.strip_rows,
-                       (int)p.npad, (float4*)w.partial);
+    hipLaunchKernelGGL(kernel, grid, dim3(kAdjThreads), 0, s, x, y, z, a, p.n, pitch, wavelength,
+                       g, ldg, p.ny, p.strip_rows, (int)p.npad, (float4*)w.partial);
   };
   if (p.adj_kind == kAdjCompensated)
     go(adj_partial_kernel<kAdjCompensated>);

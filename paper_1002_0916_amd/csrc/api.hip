@@ -432,13 +432,14 @@ int cgh_forward(const float* x, const float* y, const float* z, const float* a, 
   rc = check_workspace(p, workspace, workspace_bytes);
   if (rc) return rc;
   const Workspace w = carve(p, workspace);
-  hipError_t e = launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, false, s);
+  // The compensated forward forms the records with its row-phase table.
+  hipError_t e = variant == CGH_COMPENSATED
+                     ? launch_prep_ytab(x, y, z, a, pitch, wavelength, p, w, s)
+                     : launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, false, s);
   if (e != hipSuccess) return CGH_EHIP;
   if (variant == CGH_SEPARABLE) return forward_separable(p, w, hologram, s);
   if (half_mode(variant) >= 0) return forward_separable_half(p, w, hologram, s);
   if (variant == CGH_COMPENSATED) {
-    e = launch_ytab(p, w, s);
-    if (e != hipSuccess) return CGH_EHIP;
     const EventPair ev = profile_begin(CGH_KERNEL_FWD_COMPENSATED, s);
     e = launch_fwd_comp(p, w, hologram, s);
     profile_end(CGH_KERNEL_FWD_COMPENSATED, ev, s);
@@ -489,14 +490,18 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
   rc = check_workspace(p, workspace, workspace_bytes);
   if (rc) return rc;
   const Workspace w = carve(p, workspace);
-  hipError_t e = launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, false, s);
-  if (e != hipSuccess) return CGH_EHIP;
-  if (variant == CGH_SEPARABLE)
-    return backward_separable(p, w, z, a, pitch, wavelength, grad_hologram, grad_x, grad_y,
-                              grad_z, grad_a, s);
-  if (half_mode(variant) >= 0)
+  hipError_t e;
+  if (is_separable(variant)) {
+    e = launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, false, s);
+    if (e != hipSuccess) return CGH_EHIP;
+    if (variant == CGH_SEPARABLE)
+      return backward_separable(p, w, z, a, pitch, wavelength, grad_hologram, grad_x, grad_y,
+                                grad_z, grad_a, s);
     return backward_separable_half(p, w, z, a, pitch, wavelength, grad_hologram, grad_x, grad_y,
                                    grad_z, grad_a, s);
+  }
+  // The direct adjoint forms each point's records itself (one point per
+  // lane), so it needs no precompute launch.
   const float* g = grad_hologram;
   int64_t ldg = nx;
   if (p.need_gpad) {
@@ -511,7 +516,7 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
                   : variant == CGH_RECURRENCE ? CGH_KERNEL_ADJ_RECURRENCE
                                               : CGH_KERNEL_ADJ_PLAIN;
   const EventPair ev = profile_begin(kid, s);
-  e = launch_adj_partial(p, w, g, ldg, runs, s);
+  e = launch_adj_partial(p, w, x, y, z, a, pitch, wavelength, g, ldg, runs, s);
   profile_end(kid, ev, s);
   if (e != hipSuccess) return CGH_EHIP;
   e = launch_adj_finalize(p, w, z, a, pitch, wavelength, runs, grad_x, grad_y, grad_z, grad_a, s);

@@ -177,7 +177,11 @@ hipError_t launch_prep(const float* x, const float* y, const float* z, const flo
                        bool want64, hipStream_t s);
 hipError_t launch_fill_zero_f32(float* p, int64_t count, hipStream_t s);
 hipError_t launch_fill_zero_f64(double* p, int64_t count, hipStream_t s);
-hipError_t launch_ytab(const Plan& p, const Workspace& w, hipStream_t s);
+// The compensated forward's precompute: the point records (as launch_prep)
+// and the per-row y-phase table, in one launch.
+hipError_t launch_prep_ytab(const float* x, const float* y, const float* z, const float* a,
+                            double pitch, double wavelength, const Plan& p, const Workspace& w,
+                            hipStream_t s);
 hipError_t launch_fwd_plain(const Plan& p, const Workspace& w, float* out, hipStream_t s);
 hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s);
 hipError_t launch_fwd_rec(const Plan& p, const Workspace& w, float* out, hipStream_t s);
@@ -256,8 +260,9 @@ hipError_t launch_sep_adj_operands_half(int mode, const Plan& p, const Workspace
 // Runs per point group for this launch (<= p.regions), from the occupancy of
 // the adjoint kernel on the current device.
 int adj_runs(const Plan& p);
-hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* g, int64_t ldg,
-                              int runs, hipStream_t s);
+hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* x, const float* y,
+                              const float* z, const float* a, double pitch, double wavelength,
+                              const float* g, int64_t ldg, int runs, hipStream_t s);
 hipError_t launch_adj_finalize(const Plan& p, const Workspace& w, const float* z, const float* a,
                                double pitch, double wavelength, int runs, float* gx, float* gy,
                                float* gz, float* ga, hipStream_t s);

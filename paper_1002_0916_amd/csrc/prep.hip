@@ -1,15 +1,42 @@
-// Per-point precompute (FP64 arithmetic, O(N)) and the per-row phase table of
-// the compensated forward, plus small fill kernels.
-//
-// The phase coefficient of Eq. (1) (Section 1) is P_j = pi p^2 / (lambda z_j)
-// in radians per pixel^2; the kernels work in revolutions, so the record holds
-// Prev_j = P_j / (2 pi) = p^2 / (2 lambda z_j).
+// Per-point precompute (FP64 arithmetic, O(N)), the per-row phase table of
+// the compensated forward (fused with the precompute), and small fill
+// kernels.  The records themselves are defined in records.h.
 #include "cgh_internal.h"
 #include "phase.h"
+#include "records.h"
 
 namespace cgh {
 
 namespace {
+
+// Writes point j's records (plain, amp, axis records, optional FP64 record).
+__device__ __forceinline__ void store_records(const PointRecord& r, int64_t j,
+                                              float4* __restrict__ plain,
+                                              float* __restrict__ amp, float* __restrict__ xrec,
+                                              float* __restrict__ yrec,
+                                              double4* __restrict__ rec64) {
+  plain[j] = make_float4(r.x, r.y, r.ph, r.a);
+  amp[j] = r.a;
+  float* rx = xrec + j * kAxisRec;
+  float* ry = yrec + j * kAxisRec;
+  rx[0] = r.xc;
+  rx[1] = r.ph;
+  rx[2] = r.pl;
+  rx[3] = r.xb;
+  rx[4] = r.xd;
+  rx[5] = r.a;
+  rx[6] = r.x;
+  rx[7] = 0.0f;
+  ry[0] = r.yc;
+  ry[1] = r.ph;
+  ry[2] = r.pl;
+  ry[3] = r.yb;
+  ry[4] = r.yd;
+  ry[5] = r.a;
+  ry[6] = r.y;
+  ry[7] = 0.0f;
+  if (rec64) rec64[j] = make_double4((double)r.x, (double)r.y, r.prev, (double)r.a);
+}
 
 __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ x,
                                                    const float* __restrict__ y,
@@ -25,55 +52,28 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ x,
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (clear && j == 0) *clear = 0u;
   if (j >= npad) return;
-  // Padding points have zero amplitude at a valid position, so they add
-  // exactly 0 to every sum.
-  float xs = 0.0f, ys = 0.0f, zs = 1.0f, as = 0.0f;
-  if (j < n) {
-    xs = x[j];
-    ys = y[j];
-    zs = z[j];
-    as = a[j];
-  }
-  const double prev = (pitch * pitch) / (2.0 * wavelength * (double)zs);
-  const float ph = (float)prev;
-  const float pl = (float)(prev - (double)ph);
-  plain[j] = make_float4(xs, ys, ph, as);
-  amp[j] = as;
-
-  const float xc = rintf(xs), yc = rintf(ys);
-  const double xf = (double)(xs - xc), yf = (double)(ys - yc);  // both exact
-  float* rx = xrec + j * kAxisRec;
-  float* ry = yrec + j * kAxisRec;
-  rx[0] = xc;
-  rx[1] = ph;
-  rx[2] = pl;
-  rx[3] = (float)(-2.0 * prev * xf);
-  rx[4] = (float)(prev * xf * xf);
-  rx[5] = as;
-  rx[6] = xs;
-  rx[7] = 0.0f;
-  ry[0] = yc;
-  ry[1] = ph;
-  ry[2] = pl;
-  ry[3] = (float)(-2.0 * prev * yf);
-  ry[4] = (float)(prev * yf * yf);
-  ry[5] = as;
-  ry[6] = ys;
-  ry[7] = 0.0f;
-  if (rec64) rec64[j] = make_double4((double)xs, (double)ys, prev, (double)as);
+  store_records(point_record(x, y, z, a, j, n, pitch, wavelength), j, plain, amp, xrec, yrec,
+                rec64);
 }
 
-// ytab[g][j][i] = y-axis phase of point j at row g * kCompRows + i.
-__global__ __launch_bounds__(256) void ytab_kernel(const float* __restrict__ yrec, int64_t npad,
-                                                   int64_t total, float* __restrict__ ytab) {
+// The compensated forward's precompute in one launch: thread (g, j) forms
+// point j's records, writes them when g = 0, and writes the y-axis phases of
+// point j at the kCompRows rows of row group g:
+//   ytab[g][j][i] = axis_phase(g * kCompRows + i) of point j.
+__global__ __launch_bounds__(256) void prep_ytab_kernel(
+    const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
+    const float* __restrict__ a, int64_t n, int64_t npad, int64_t groups, double pitch,
+    double wavelength, float4* __restrict__ plain, float* __restrict__ amp,
+    float* __restrict__ xrec, float* __restrict__ yrec, float* __restrict__ ytab) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  const int64_t i = t % kCompRows;
-  const int64_t j = (t / kCompRows) % npad;
-  const int64_t g = t / (kCompRows * npad);
-  const float* r = yrec + j * kAxisRec;
-  const float h = (float)(g * kCompRows + i);
-  ytab[t] = axis_phase(h, r[0], r[1], r[2], r[3], r[4]);
+  if (t >= groups * npad) return;
+  const int64_t g = t / npad, j = t - g * npad;
+  const PointRecord r = point_record(x, y, z, a, j, n, pitch, wavelength);
+  if (g == 0) store_records(r, j, plain, amp, xrec, yrec, nullptr);
+  float* dst = ytab + t * kCompRows;
+#pragma unroll
+  for (int i = 0; i < kCompRows; ++i)
+    dst[i] = axis_phase((float)(g * kCompRows + i), r.yc, r.ph, r.pl, r.yb, r.yd);
 }
 
 __global__ __launch_bounds__(256) void zero_f32_kernel(float* __restrict__ p, int64_t count) {
@@ -101,10 +101,13 @@ hipError_t launch_prep(const float* x, const float* y, const float* z, const flo
   return hipGetLastError();
 }
 
-hipError_t launch_ytab(const Plan& p, const Workspace& w, hipStream_t s) {
-  const int64_t total = (int64_t)p.groups * p.npad * kCompRows;
-  hipLaunchKernelGGL(ytab_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, w.yrec, p.npad,
-                     total, w.ytab);
+hipError_t launch_prep_ytab(const float* x, const float* y, const float* z, const float* a,
+                            double pitch, double wavelength, const Plan& p, const Workspace& w,
+                            hipStream_t s) {
+  const int64_t total = (int64_t)p.groups * p.npad;
+  hipLaunchKernelGGL(prep_ytab_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, x, y, z, a,
+                     p.n, p.npad, (int64_t)p.groups, pitch, wavelength, w.plain, w.amp, w.xrec,
+                     w.yrec, w.ytab);
   return hipGetLastError();
 }
 
