@@ -217,7 +217,9 @@ __global__ __launch_bounds__(256) void pad_g_kernel(const float* __restrict__ g,
 hipError_t launch_pad_g(const Plan& p, const float* g, float* gpad, hipStream_t s) {
   const int ldp = p.nsx * kAdjCols;
   const int64_t total = (int64_t)ldp * p.ny;
-  hipLaunchKernelGGL(pad_g_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g,
+  const unsigned blocks = grid_blocks(total, 256);
+  if (!blocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pad_g_kernel, dim3(blocks), dim3(256), 0, s, g,
                      p.nx, p.ny, ldp, total, gpad);
   return hipGetLastError();
 }

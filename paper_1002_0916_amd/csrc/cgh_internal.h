@@ -24,6 +24,14 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned i, unsigned n) {
   return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
 }
 
+// Workgroups of `threads` covering `count` items on a 1-D grid, or 0 when
+// that exceeds the grid's x limit (2^31 - 1); launchers then return
+// hipErrorInvalidValue instead of launching a truncated grid.
+inline unsigned grid_blocks(int64_t count, int threads) {
+  const int64_t b = (count + threads - 1) / threads;
+  return (b < 1 || b > 0x7fffffff) ? 0u : (unsigned)b;
+}
+
 // ---------------------------------------------------------------- forward --
 // Plain forward: a workgroup is 4 waves.  Lane l of every wave owns hologram
 // column x0 + l; wave w owns kRows consecutive rows, so a workgroup covers 64

@@ -316,7 +316,9 @@ hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStr
 
 hipError_t launch_fwd_f64(const Plan& p, const Workspace& w, double* out, hipStream_t s) {
   const int64_t npix = (int64_t)p.nx * p.ny;
-  hipLaunchKernelGGL(fwd_f64_kernel, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s,
+  const unsigned blocks = grid_blocks(npix, 256);
+  if (!blocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fwd_f64_kernel, dim3(blocks), dim3(256), 0, s,
                      (const double4*)w.rec64, (int)p.npad, p.nx, npix, out);
   return hipGetLastError();
 }

@@ -86,16 +86,12 @@ __global__ __launch_bounds__(256) void zero_f64_kernel(double* __restrict__ p, i
   if (t < count) p[t] = 0.0;
 }
 
-inline unsigned blocks_for(int64_t count, int threads) {
-  return (unsigned)((count + threads - 1) / threads);
-}
-
 }  // namespace
 
 hipError_t launch_prep(const float* x, const float* y, const float* z, const float* a, int64_t n,
                        int64_t npad, double pitch, double wavelength, const Workspace& w,
                        bool want64, hipStream_t s) {
-  hipLaunchKernelGGL(prep_kernel, dim3(blocks_for(npad, 256)), dim3(256), 0, s, x, y, z, a, n,
+  hipLaunchKernelGGL(prep_kernel, dim3(grid_blocks(npad, 256)), dim3(256), 0, s, x, y, z, a, n,
                      npad, pitch, wavelength, w.plain, w.amp, w.xrec, w.yrec,
                      want64 ? w.rec64 : (double4*)nullptr, w.hmax);
   return hipGetLastError();
@@ -105,7 +101,9 @@ hipError_t launch_prep_ytab(const float* x, const float* y, const float* z, cons
                             double pitch, double wavelength, const Plan& p, const Workspace& w,
                             hipStream_t s) {
   const int64_t total = (int64_t)p.groups * p.npad;
-  hipLaunchKernelGGL(prep_ytab_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, x, y, z, a,
+  const unsigned blocks = grid_blocks(total, 256);
+  if (!blocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(prep_ytab_kernel, dim3(blocks), dim3(256), 0, s, x, y, z, a,
                      p.n, p.npad, (int64_t)p.groups, pitch, wavelength, w.plain, w.amp, w.xrec,
                      w.yrec, w.ytab);
   return hipGetLastError();
@@ -113,13 +111,17 @@ hipError_t launch_prep_ytab(const float* x, const float* y, const float* z, cons
 
 hipError_t launch_fill_zero_f32(float* p, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(zero_f32_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, s, p, count);
+  const unsigned blocks = grid_blocks(count, 256);
+  if (!blocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(zero_f32_kernel, dim3(blocks), dim3(256), 0, s, p, count);
   return hipGetLastError();
 }
 
 hipError_t launch_fill_zero_f64(double* p, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(zero_f64_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, s, p, count);
+  const unsigned blocks = grid_blocks(count, 256);
+  if (!blocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(zero_f64_kernel, dim3(blocks), dim3(256), 0, s, p, count);
   return hipGetLastError();
 }
 

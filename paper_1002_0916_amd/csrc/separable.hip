@@ -142,16 +142,12 @@ __global__ __launch_bounds__(kWave* kFinSlices) void sep_finalize_kernel(
   gz[j] = (float)(aj * P / zj * Sr);
 }
 
-inline unsigned blocks_for(int64_t count, int threads) {
-  return (unsigned)((count + threads - 1) / threads);
-}
-
 }  // namespace
 
 dim3 table_grid(int64_t npad, int rows) {
   // About 1024 workgroups: enough to fill the chip, few enough that each
   // thread reuses its point's records over many rows.
-  const unsigned bx = blocks_for(npad, 256);
+  const unsigned bx = grid_blocks(npad, 256);
   unsigned gy = bx >= 1024 ? 1 : 1024 / bx;
   if (gy > (unsigned)rows) gy = (unsigned)rows;
   return dim3(bx, gy);
@@ -168,15 +164,19 @@ hipError_t launch_sep_tables(const float* xrec, const float* yrec, const float* 
 
 hipError_t launch_sep_sum_slices(const float* C, int splits, int64_t slice_stride, int64_t ldc,
                                  int nx, int ny, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(sep_sum_slices_kernel, dim3(blocks_for((int64_t)nx * ny, 256)), dim3(256), 0,
-                     s, C, splits, slice_stride, ldc, nx, ny, out);
+  const unsigned blocks = grid_blocks((int64_t)nx * ny, 256);
+  if (!blocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sep_sum_slices_kernel, dim3(blocks), dim3(256), 0, s, C, splits, slice_stride,
+                     ldc, nx, ny, out);
   return hipGetLastError();
 }
 
 hipError_t launch_sep_pad(const float* g, int nx, int ny, int rows_pad, int cols_pad, float* gp,
                           hipStream_t s) {
   const int64_t total = (int64_t)rows_pad * cols_pad;
-  hipLaunchKernelGGL(sep_pad_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, g, nx, ny,
+  const unsigned blocks = grid_blocks(total, 256);
+  if (!blocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sep_pad_kernel, dim3(blocks), dim3(256), 0, s, g, nx, ny,
                      cols_pad, total, gp);
   return hipGetLastError();
 }
@@ -186,7 +186,7 @@ hipError_t launch_sep_finalize(const Plan& p, const Workspace& w, const float* z
                                float* ga, hipStream_t s) {
   const int planes_x = p.sep_splits_u * (p.nxp / 128);
   const int planes_y = p.sep_splits_p * (p.nyp / 128);
-  hipLaunchKernelGGL(sep_finalize_kernel, dim3(blocks_for(p.n, kWave)), dim3(kWave, kFinSlices),
+  hipLaunchKernelGGL(sep_finalize_kernel, dim3(grid_blocks(p.n, kWave)), dim3(kWave, kFinSlices),
                      0, s,
                      (const float4*)w.fold_x, planes_x, (const float4*)w.fold_y, planes_y, p.npad,
                      p.n, z, a, pitch, wavelength, gx, gy, gz, ga);

@@ -30,10 +30,6 @@ namespace cgh {
 
 namespace {
 
-inline unsigned blocks_for(int64_t count, int threads) {
-  return (unsigned)((count + threads - 1) / threads);
-}
-
 // Rounds v (|v| <= 1) to the 16-bit format of MODE; lo is the fp16 residual
 // in kHalfF16x3 mode and 0 otherwise.
 template <int MODE>
@@ -242,7 +238,7 @@ hipError_t launch_sep_tables_half(int mode, const Plan& p, const Workspace& w, h
 // About 1024 table workgroups (point strides of tab_rows), then the tiles.
 hipError_t launch_sep_adj_operands_half(int mode, const Plan& p, const Workspace& w,
                                         const float* g, hipStream_t s) {
-  const int tab_blocks = (int)blocks_for(p.nxp + p.nyp, 256);
+  const int tab_blocks = (int)grid_blocks(p.nxp + p.nyp, 256);
   int tab_rows = tab_blocks >= 1024 ? 1 : 1024 / tab_blocks;
   if (tab_rows > p.npad) tab_rows = (int)p.npad;
   const int tiles = (p.nxp / 64) * (p.nyp / 64);
