@@ -794,17 +794,17 @@ def summarize_stats(root):
 # (bench.py reports a kernel's traffic only while these hash the same) and
 # the algorithmic bytes of one launch at the headline workload.
 TRAFFIC_KERNELS = {
-    "adj_partial_kernel<1>": (["adjoint.hip", "phase.h", "cgh_internal.h"],
-                              "G 7.86 MB + records 0.08 MB + run partials 12.6 MB"),
-    "adj_partial_kernel<0>": (["adjoint.hip", "phase.h", "cgh_internal.h"], "same"),
-    "adj_partial_kernel<2>": (["adjoint.hip", "phase.h", "cgh_internal.h"], "same"),
+    "adj_partial_kernel<1>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"],
+                              "G 7.86 MB + inputs 0.02 MB + run partials 12.6 MB"),
+    "adj_partial_kernel<0>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"], "same"),
+    "adj_partial_kernel<2>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"], "same"),
     "fwd_comp_kernel": (["forward.hip", "phase.h", "cgh_internal.h"],
                         "row table 4.19 MB + records 0.05 MB + hologram 7.86 MB"),
     "fwd_plain_kernel": (["forward.hip", "phase.h", "cgh_internal.h"],
                          "records 0.02 MB + hologram 7.86 MB"),
     "fwd_rec_kernel<8, 4>": (["forward.hip", "phase.h", "cgh_internal.h"],
                              "records 0.02 MB + hologram 7.86 MB"),
-    "prep_kernel": (["prep.hip", "phase.h", "cgh_internal.h"],
+    "prep_kernel": (["prep.hip", "phase.h", "records.h", "cgh_internal.h"],
                     "inputs 0.02 MB + records 0.2 MB (+ f64 records)"),
     "gemm_f32_kernel<true, true, 0>": (["gemm.hip", "fold.h", "phase.h", "cgh_internal.h"],
                                        "tables 8.4 + 15.7 MB + split planes (forward)"),
