@@ -73,10 +73,11 @@ static_assert(kWave % kCompWaves == 0, "x-phase fill splits the 64 columns over 
 static_assert(kTile % (2 * kCompUnroll) == 0, "tiles hold whole ping-pong group pairs");
 constexpr int kPointPad = 64;
 
-// Recurrence forward (Eq. (2)): lane l of a wave covers kRecK consecutive
-// pixels of kRecR rows, a workgroup kRecWaves waves stacked in y; points are
-// taken kRecUnroll at a time (scalar loads one group ahead).  (K, R) comes
-// from a small set of instantiations chosen per shape by rec_shape().
+// Recurrence forward (Eq. (2)): lane l of a wave covers K consecutive pixels
+// of R rows, a group of kRecWaves waves is stacked in y, and a workgroup holds
+// S such groups that split the points between them; points are taken
+// kRecUnroll at a time (scalar loads one group ahead).  (K, R) comes from a
+// small set of instantiations chosen per shape by rec_shape().
 constexpr int kRecWaves = 4;
 constexpr int kRecThreads = kRecWaves * kWave;
 constexpr int kRecUnroll = 4;
@@ -160,7 +161,7 @@ struct Plan {
   int32_t variant, op;
   // forward
   int32_t fwd_gx, fwd_gy, comp_gy, groups;
-  int32_t rec_k, rec_r, rec_gx, rec_gy;  // recurrence forward shape and grid
+  int32_t rec_k, rec_r, rec_s, rec_gx, rec_gy;  // recurrence forward shape, split, grid
   // adjoint: runs of strip-rows per point group (regions = the most runs the
   // partial buffer holds; the launch may use fewer)
   int32_t nsx, regions, ngroups, adj_kind;

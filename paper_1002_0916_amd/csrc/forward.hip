@@ -73,12 +73,20 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_plain_kernel(const float4* __
 // exact-reduction range without a fract per step.  Points are read four at a
 // time through scalar loads (the paper unrolls four points per iteration),
 // one group ahead of their use.
-template <int K, int R>
-__global__ __launch_bounds__(kRecThreads) void fwd_rec_kernel(const float4* __restrict__ rec,
-                                                              int npad, int nx, int ny,
-                                                              float* __restrict__ out) {
+//
+// S > 1 splits the points of a workgroup's pixels over S groups of kRecWaves
+// waves (point subset s = [s npad / S, (s + 1) npad / S)): more waves per SIMD
+// for the same pixels, when the hologram is too small to give every SIMD
+// several.  Groups 1 .. S-1 leave their sums in LDS and group 0 adds them in
+// group order and stores (deterministic).
+template <int K, int R, int S>
+__global__ __launch_bounds__(kRecThreads * S) void fwd_rec_kernel(const float4* __restrict__ rec,
+                                                                  int npad, int nx, int ny,
+                                                                  float* __restrict__ out) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wave_all = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wave = wave_all % kRecWaves;  // rows
+  const int part = wave_all / kRecWaves;  // point subset
   // Row blocks run along the grid's x dimension (up to 2^20 / 4 of them),
   // column blocks along y.
   const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
@@ -117,24 +125,48 @@ __global__ __launch_bounds__(kRecThreads) void fwd_rec_kernel(const float4* __re
   // Two ping-pong groups of records in SGPRs; the next group's loads are
   // issued after the first point of the current one (whose use waits for
   // every outstanding scalar load), so the other points cover their latency.
-  // The last group re-reads itself (in bounds).
+  // The last group of the subset re-reads itself (in bounds).
   auto load = [&](int j, float4* dst) {
 #pragma unroll
     for (int u = 0; u < kRecUnroll; ++u) dst[u] = rec[j + u];
   };
-  auto group = [&](int j, const float4* cur, float4* nxt) {
+  auto group = [&](int j, const float4* cur, float4* nxt, int jend) {
     point(cur[0]);
     __builtin_amdgcn_sched_barrier(0);
-    load(min(j + kRecUnroll, npad - kRecUnroll), nxt);
+    load(min(j + kRecUnroll, jend - kRecUnroll), nxt);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 1; u < kRecUnroll; ++u) point(cur[u]);
   };
+  const int jbeg = part * (npad / S), jend = jbeg + npad / S;
   float4 A[kRecUnroll], B[kRecUnroll];
-  load(0, A);
-  for (int j = 0; j < npad; j += 2 * kRecUnroll) {
-    group(j, A, B);
-    group(j + kRecUnroll, B, A);
+  load(jbeg, A);
+  for (int j = jbeg; j < jend; j += 2 * kRecUnroll) {
+    group(j, A, B, jend);
+    group(j + kRecUnroll, B, A, jend);
+  }
+  if constexpr (S > 1) {
+    // [subset - 1][element][thread of the group]: consecutive lanes hit
+    // consecutive words.
+    constexpr int kGroupThreads = kRecThreads;
+    __shared__ float part_sums[(S - 1) * R * K * kGroupThreads];
+    const int t = wave * kWave + lane;
+    if (part > 0) {
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int n = 0; n < K; ++n)
+          part_sums[((part - 1) * R * K + i * K + n) * kGroupThreads + t] = acc[i][n];
+    }
+    __syncthreads();
+    if (part > 0) return;
+#pragma unroll
+    for (int q = 1; q < S; ++q)
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int n = 0; n < K; ++n)
+          acc[i][n] += part_sums[((q - 1) * R * K + i * K + n) * kGroupThreads + t];
   }
 #pragma unroll
   for (int i = 0; i < R; ++i) {
@@ -285,8 +317,12 @@ namespace {
 
 template <int K, int R>
 hipError_t launch_rec(const Plan& p, const Workspace& w, float* out, hipStream_t s) {
-  hipLaunchKernelGGL((fwd_rec_kernel<K, R>), dim3(p.rec_gy, p.rec_gx), dim3(kRecThreads), 0, s,
-                     (const float4*)w.plain, (int)p.npad, p.nx, p.ny, out);
+  if (p.rec_s == 2)
+    hipLaunchKernelGGL((fwd_rec_kernel<K, R, 2>), dim3(p.rec_gy, p.rec_gx), dim3(kRecThreads * 2),
+                       0, s, (const float4*)w.plain, (int)p.npad, p.nx, p.ny, out);
+  else
+    hipLaunchKernelGGL((fwd_rec_kernel<K, R, 1>), dim3(p.rec_gy, p.rec_gx), dim3(kRecThreads), 0,
+                       s, (const float4*)w.plain, (int)p.npad, p.nx, p.ny, out);
   return hipGetLastError();
 }
 
