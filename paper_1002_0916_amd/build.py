@@ -57,6 +57,23 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+PROBE_SRC = os.path.join(HERE, "probe", "issue_rates.hip")
+PROBE_BIN = os.path.join(HERE, "probe", "issue_rates")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """Builds the machine-constant probe (a standalone program, not part of
+    the library): FP32 issue rates of FMA and the transcendentals, and their
+    accuracy."""
+    cmd = [HIPCC, *HIPFLAGS, PROBE_SRC, "-o", PROBE_BIN]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s" % (PROBE_SRC, r.stderr))
+    if verbose:
+        print("built", PROBE_BIN)
+    return PROBE_BIN
+
+
 def dump_isa(out_dir: str) -> None:
     """Writes the gfx950 assembly of every source to ``out_dir`` (inspection)."""
     os.makedirs(out_dir, exist_ok=True)
