@@ -140,10 +140,12 @@ def copy_reference(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "copies": 5}), flush=True)
 
 
-def measured_traffic(kernel, path=None):
+def measured_traffic(kernel, path=None, key="traffic_bytes"):
     """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
-    record (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy reference), or
-    None when the kernel's sources have changed since the counters were taken."""
+    record, or None when the kernel's sources have changed since the counters
+    were taken.  ``traffic_bytes``: FETCH_SIZE and WRITE_SIZE scaled by a
+    plain-copy reference; ``traffic_bytes_sized``: reads counted by request
+    size (32, 64 and 128 bytes) plus the same writes."""
     if path is None:
         path = os.path.join(ROOT, "profiles", "traffic_paper_1920x1024_n1024.json")
     try:
@@ -153,7 +155,7 @@ def measured_traffic(kernel, path=None):
         return None
     if _sources_hash(rec["sources"]) != rec["source_sha256_16"]:
         return None
-    return rec["traffic_bytes"]
+    return rec.get(key)
 
 
 # Device-code names of the direct adjoint kernels (the roofline kernel).
@@ -368,6 +370,11 @@ def main():
                         if args.variant in ADJ_KERNEL_NAME else None),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                             "copy-calibrated)",
+            "traffic_sized": (measured_traffic(ADJ_KERNEL_NAME[args.variant],
+                                               key="traffic_bytes_sized")
+                              if args.variant in ADJ_KERNEL_NAME else None),
+            "traffic_sized_unit": "bytes per launch (reads: TCC_EA0_RDREQ_32B/64B/128B x "
+                                  "request size; writes: copy-calibrated WRITE_SIZE)",
             "slots_per_interaction": SLOTS.get(adj_key),
             "frac_if_packed": (achieved * 1e9 / (PEAK_SLOTS / SLOTS_PACKED[adj_key])
                                if adj_key in SLOTS_PACKED else None),
@@ -860,6 +867,20 @@ def summarize_traffic(root):
     copy_f = cf["__amd_rocclr_copyBuffer"]["FETCH_SIZE"]
     copy_w = cw["__amd_rocclr_copyBuffer"]["WRITE_SIZE"]
     ff, wf = copy_f * 1024 / copy_bytes, copy_w * 1024 / copy_bytes
+    # Read requests by size (optional pass): FETCH_SIZE's gfx950 formula counts
+    # a 128-byte request as 64 bytes, so the copy-derived factor is right only
+    # for kernels whose reads come in 128-byte requests.
+    rq = cq = {}
+    if os.path.isdir(os.path.join(root, "rdreq")):
+        rq = _counter_means(_csv_files(os.path.join(root, "rdreq"), "*counter_collection.csv"))
+        cq = _counter_means(_csv_files(os.path.join(root, "copy_rdreq"),
+                                       "*counter_collection.csv"))
+
+    def sized(c):
+        return (32 * c["TCC_EA0_RDREQ_32B_sum"] + 64 * c["TCC_EA0_RDREQ_64B_sum"]
+                + 128 * c["TCC_EA0_RDREQ_128B_sum"])
+
+    copy_sized = sized(cq["__amd_rocclr_copyBuffer"]) if "__amd_rocclr_copyBuffer" in cq else None
     kernels = {}
     for k, (sources, _) in TRAFFIC_KERNELS.items():
         if k not in fe or k not in wr:
@@ -870,9 +891,17 @@ def summarize_traffic(root):
                       "fetch_bytes": f_raw * 1024 / ff, "write_bytes": w_raw * 1024 / wf,
                       "traffic_bytes": f_raw * 1024 / ff + w_raw * 1024 / wf,
                       "source_sha256_16": _sources_hash(sources), "sources": sources}
+        if k in rq:
+            c = rq[k]
+            kernels[k].update({
+                "read_requests": {"32B": c["TCC_EA0_RDREQ_32B_sum"],
+                                  "64B": c["TCC_EA0_RDREQ_64B_sum"],
+                                  "128B": c["TCC_EA0_RDREQ_128B_sum"]},
+                "read_bytes_sized": sized(c),
+                "traffic_bytes_sized": sized(c) + w_raw * 1024 / wf})
     rec = {"workload": "1920x1024 hologram, N=1024 points (bench.py step)",
            "copy_reference_bytes": copy_bytes, "fetch_factor": ff, "write_factor": wf,
-           "kernels": kernels}
+           "copy_read_bytes_sized": copy_sized, "kernels": kernels}
     with open(os.path.join(PROFILES, "traffic_paper_1920x1024_n1024.json"), "w") as f:
         json.dump(rec, f, indent=1)
     runs = [("fetch", "FETCH_SIZE", "bench.py --steps 3 --warmup 1 --no-cpu-baseline"),
@@ -882,6 +911,9 @@ def summarize_traffic(root):
     lines = ["# HBM traffic per launch: bench.py step at 1920x1024, N=1024", "",
              "Commands (from the repository root on an MI355X machine, one counter per run), then "
              "`python bench.py --summarize traffic <out>`:", "", "```", _ROCPROF.rstrip(" &")]
+    if rq:
+        runs += [("rdreq", RDREQ_COUNTERS, "bench.py --steps 3 --warmup 1 --no-cpu-baseline"),
+                 ("copy_rdreq", RDREQ_COUNTERS, "bench.py --copy-bytes %d" % copy_bytes)]
     for d, counter, cmd in runs:
         lines.append("timeout -s KILL 150 rocprofv3 --kernel-trace --pmc %s -f csv -d <out>/%s "
                      "-o %s -- python3 %s" % (counter, d, d, cmd))
@@ -900,8 +932,31 @@ def summarize_traffic(root):
         lines.append("| %s | %.0f | %.0f | %.2f MB | %.2f MB | %.2f MB | %s |" % (
             k, v["fetch_kib_raw"], v["write_kib_raw"], v["fetch_bytes"] / 1e6,
             v["write_bytes"] / 1e6, v["traffic_bytes"] / 1e6, TRAFFIC_KERNELS[k][1]))
+    if rq:
+        lines += ["", "## Reads by request size", "",
+                  "On gfx950 the FETCH_SIZE expression counts a 128-byte read request as 64 bytes "
+                  "(the copy above reads %.4f of its bytes), so the copy factor is exact only for "
+                  "128-byte requests.  Scalar loads (the direct kernels' point records and rows "
+                  "of G) come in 64-byte requests, which FETCH_SIZE already counts in full, and "
+                  "the copy factor doubles them.  Counting each request at its size "
+                  "(TCC_EA0_RDREQ_32B, _64B, _128B) gives the reads below; the copy reads %.1f MB "
+                  "of its %.1f MB this way."
+                  % (ff, (copy_sized or 0) / 1e6, copy_bytes / 1e6), "",
+                  "| kernel | 32 B requests | 64 B requests | 128 B requests | reads (sized) | "
+                  "reads (copy-scaled FETCH_SIZE) | total (sized reads + writes) |",
+                  "|---|---|---|---|---|---|---|"]
+        for k, v in kernels.items():
+            if "read_bytes_sized" not in v:
+                continue
+            r = v["read_requests"]
+            lines.append("| %s | %.0f | %.0f | %.0f | %.2f MB | %.2f MB | %.2f MB |" % (
+                k, r["32B"], r["64B"], r["128B"], v["read_bytes_sized"] / 1e6,
+                v["fetch_bytes"] / 1e6, v["traffic_bytes_sized"] / 1e6))
     _write_md("traffic_paper_1920x1024_n1024.md", lines)
 
+
+RDREQ_COUNTERS = ("TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum "
+                  "TCC_EA0_RDREQ_sum")
 
 COUNTER_PASSES = (
     "SQ_INSTS_VALU SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_SALU SQ_INSTS_SMEM SQ_INSTS_LDS SQ_WAVES "

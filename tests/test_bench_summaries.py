@@ -70,6 +70,41 @@ def test_traffic_is_copy_calibrated_and_withheld_when_sources_change(bench, tmp_
     assert bench.measured_traffic("adj_partial_kernel<1>", path) is None
 
 
+def test_traffic_counts_read_requests_at_their_size(bench, tmp_path):
+    run = tmp_path / "run"
+    _counters(run / "fetch" / "f_counter_collection.csv", [(ADJ1, "FETCH_SIZE", 1000)])
+    _counters(run / "write" / "w_counter_collection.csv", [(ADJ1, "WRITE_SIZE", 500)])
+    _counters(run / "copy_fetch" / "c_counter_collection.csv",
+              [("__amd_rocclr_copyBuffer", "FETCH_SIZE", 131072)])
+    _counters(run / "copy_write" / "c_counter_collection.csv",
+              [("__amd_rocclr_copyBuffer", "WRITE_SIZE", 262144)])
+    # the kernel: 10 32-byte, 1000 64-byte and 3 128-byte read requests
+    _counters(run / "rdreq" / "r_counter_collection.csv",
+              [(ADJ1, "TCC_EA0_RDREQ_32B_sum", 10), (ADJ1, "TCC_EA0_RDREQ_64B_sum", 1000),
+               (ADJ1, "TCC_EA0_RDREQ_128B_sum", 3), (ADJ1, "TCC_EA0_RDREQ_sum", 1013)])
+    _counters(run / "copy_rdreq" / "c_counter_collection.csv",
+              [("__amd_rocclr_copyBuffer", "TCC_EA0_RDREQ_32B_sum", 0),
+               ("__amd_rocclr_copyBuffer", "TCC_EA0_RDREQ_64B_sum", 0),
+               ("__amd_rocclr_copyBuffer", "TCC_EA0_RDREQ_128B_sum", 2097152),
+               ("__amd_rocclr_copyBuffer", "TCC_EA0_RDREQ_sum", 2097152)])
+    bench.summarize("traffic", str(run))
+    path = os.path.join(bench.PROFILES, "traffic_paper_1920x1024_n1024.json")
+    with open(path) as f:
+        rec = json.load(f)
+    assert rec["copy_read_bytes_sized"] == 268435456
+    k = rec["kernels"]["adj_partial_kernel<1>"]
+    assert k["read_bytes_sized"] == 10 * 32 + 1000 * 64 + 3 * 128
+    sized = 10 * 32 + 1000 * 64 + 3 * 128 + 500 * 1024
+    assert bench.measured_traffic("adj_partial_kernel<1>", path,
+                                  key="traffic_bytes_sized") == pytest.approx(sized)
+    # the copy-calibrated figure is unchanged
+    assert bench.measured_traffic("adj_partial_kernel<1>", path) == pytest.approx(
+        1000 * 1024 / 0.5 + 500 * 1024)
+    with open(os.path.join(bench.PROFILES, "traffic_paper_1920x1024_n1024.md")) as f:
+        text = f.read()
+    assert "| adj_partial_kernel<1> | 10 | 1000 | 3 |" in text
+
+
 def test_counter_summary_per_interaction(bench, tmp_path):
     run = tmp_path / "ctr"
     n = bench.HEADLINE_INTERACTIONS
