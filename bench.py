@@ -750,13 +750,15 @@ def summarize_stats(root):
     for f in _csv_files(root, "*kernel_stats.csv"):
         with open(f) as fh:
             rows += list(csv.DictReader(fh))
-    cmd = (_ROCPROF + "timeout -s KILL 150 rocprofv3 --kernel-trace --stats -f csv -d <out>/stats "
-           "-o bench -- python3 bench.py --steps 10 --warmup 2 --no-cpu-baseline")
+    cmd = (_ROCPROF + "timeout -s KILL 400 rocprofv3 --kernel-trace --stats -f csv -d <out>/stats "
+           "-o bench -- python3 bench.py > <out>/stats/bench_stdout.log")
     lines = ["# Kernel stats: bench.py step at 1920x1024, N=1024", "",
-             "Command (run from the repository root on an MI355X machine), then "
-             "`python bench.py --summarize stats <out>/stats`:", "", "```", cmd, "```", "",
-             "The run times every variant of the step (10 timed + 2 warm-up steps each, one "
-             "graph capture and 10 replays per variant, and the accuracy checks).  Kernel "
+             "Command (run from the repository root on an MI355X machine): the default benchmark "
+             "command under the kernel tracer, then `python bench.py --summarize stats "
+             "<out>/stats`:", "", "```", cmd, "```", "",
+             "The run times every variant of the step (50 timed + 5 warm-up steps each, one "
+             "graph capture and 50 replays per variant, the accuracy checks and the CPU "
+             "baseline).  Kernel "
              "names: fwd_comp_kernel / adj_partial_kernel<1> (compensated), fwd_plain_kernel / "
              "adj_partial_kernel<0> (plain), fwd_rec_kernel<K, R> / adj_partial_kernel<2> "
              "(recurrence), gemm_f32_kernel (separable FP32), gemm_half_kernel<format, fold> "
@@ -769,12 +771,22 @@ def summarize_stats(root):
             float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
     # The JSON line that the profiled command printed (saved beside the CSVs
     # as *.log): its HIP-event kernel means, taken in the same run.
-    line = None
-    for f in _csv_files(root, "*.log"):
-        with open(f) as fh:
+    def json_line(path):
+        found = None
+        with open(path) as fh:
             for text in fh:
                 if text.startswith("{") and '"variants"' in text:
-                    line = json.loads(text)
+                    found = json.loads(text)
+        return found
+
+    # bench_stdout.log: the profiled command's own line; unprofiled.log
+    # (optional): the same command run without the profiler.
+    line = unprof = None
+    for f in _csv_files(root, "*.log"):
+        if os.path.basename(f) == "unprofiled.log":
+            unprof = json_line(f)
+        else:
+            line = json_line(f) or line
     if line is not None:
         traced = {_kernel_short(r["Name"]): float(r["AverageNs"]) / 1e3 for r in rows}
         pairs = [("fwd_comp_kernel", "compensated", "fwd"),
@@ -784,16 +796,25 @@ def summarize_stats(root):
                  ("adj_partial_kernel<2>", "recurrence", "adj")]
         lines += ["", "Agreement with the HIP events that bench.py records around the same kernels "
                   "in the same profiled run (mean of the timed steps' launches; the trace "
-                  "average also covers warm-up, graph-replay and accuracy-check launches):", "",
-                  "| kernel | traced avg us | HIP-event mean us | traced / event |",
-                  "|---|---|---|---|"]
+                  "average also covers warm-up, graph-replay and accuracy-check launches)"
+                  + (", and with the same command run without the profiler" if unprof else "")
+                  + ":", "",
+                  "| kernel | traced avg us | HIP-event mean us | traced / event |"
+                  + (" unprofiled HIP-event mean us | traced / unprofiled |" if unprof else ""),
+                  "|---|---|---|---|" + ("---|---|" if unprof else "")]
         for k, v, op in pairs:
             ev = line["variants"].get(v, {}).get(op + "_kernel_ms")
             if k in traced and ev:
-                lines.append("| %s | %.1f | %.1f | %.3f |" % (k, traced[k], ev * 1e3,
-                                                              traced[k] / (ev * 1e3)))
+                row = "| %s | %.1f | %.1f | %.3f |" % (k, traced[k], ev * 1e3,
+                                                       traced[k] / (ev * 1e3))
+                uv = unprof["variants"].get(v, {}).get(op + "_kernel_ms") if unprof else None
+                if uv:
+                    row += " %.1f | %.3f |" % (uv * 1e3, traced[k] / (uv * 1e3))
+                lines.append(row)
         lines += ["", "Profiled step of the headline (compensated) variant: %.3f ms." %
                   line["ms_per_step"]]
+        if unprof:
+            lines.append("Unprofiled step of the same command: %.3f ms." % unprof["ms_per_step"])
     _write_md("bench_paper_1920x1024_n1024_kernel_stats.md", lines)
 
 

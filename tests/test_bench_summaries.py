@@ -151,6 +151,17 @@ def test_stats_summary_compares_trace_with_events(bench, tmp_path):
         text = f.read()
     assert "| adj_partial_kernel<1> | 10 | 460.0 | 450.0 | 470.0 | 60.0% |" in text
     assert "| adj_partial_kernel<1> | 460.0 | 460.0 | 1.000 |" in text
+    # with an unprofiled run of the same command beside it, a second ratio
+    unprof = {"ms_per_step": 0.69, "variants": {"compensated": {"adj_kernel_ms": 0.4,
+                                                                "fwd_kernel_ms": 0.25}}}
+    with open(run / "unprofiled.log", "w") as f:
+        f.write(json.dumps(unprof) + "\n")
+    bench.summarize("stats", str(run))
+    with open(os.path.join(bench.PROFILES, "bench_paper_1920x1024_n1024_kernel_stats.md")) as f:
+        text = f.read()
+    assert "| adj_partial_kernel<1> | 460.0 | 460.0 | 1.000 | 400.0 | 1.150 |" in text
+    assert "Profiled step of the headline (compensated) variant: 0.700 ms." in text
+    assert "Unprofiled step of the same command: 0.690 ms." in text
 
 
 def test_summarize_rejects_unknown_kind(bench):
