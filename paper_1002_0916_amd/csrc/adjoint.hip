@@ -14,8 +14,10 @@
 // (kAdjCols floats) at a time.  The pixel-dependent factors separate by axis,
 // r^2 = dx^2 + dy^2, so per strip the lane keeps the column phases (or dx, or
 // the recurrence steps) and the column sums of G sin(theta) in registers, and
-// per row it forms the row phase (or dy^2) once and folds the row sum of
-// G sin(theta) with dy and dy^2.
+// per row it takes the row phase (or dy^2) once and folds the row sum of
+// G sin(theta) with dy and dy^2.  The compensated kind reads the row phase
+// and dy from a table built once per call (one 8-byte load per row and lane)
+// instead of forming them in every strip.
 // Per interaction that leaves the phase, sin and cos, and three fused
 // multiply-adds with G taken straight from an SGPR.
 //
@@ -35,7 +37,8 @@ namespace cgh {
 
 namespace {
 
-// KIND: kAdjPlain, kAdjCompensated or kAdjRecurrence.  With the recurrence
+// KIND: kAdjPlain, kAdjCompensated (row phases and dy from the row table),
+// kAdjCompensatedInline (the same values formed here) or kAdjRecurrence.  With the recurrence
 // (Eq. (2), Section 2.1) each strip row starts from the plain phase
 // Gamma_0 = fract(Prev r^2) at the strip's first column and steps
 // Gamma += delta_c, delta_c = Prev (2 (x_c - x_j) + 1) reduced mod 1, the
@@ -46,7 +49,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
     const float* __restrict__ a, int64_t n, double pitch, double wavelength,
     const float* __restrict__ g, int64_t ldg, int ny, int64_t strip_rows, int npad,
-    float4* __restrict__ partial) {
+    const float2* __restrict__ rtab, float4* __restrict__ partial) {
+  constexpr bool kComp = KIND == kAdjCompensated || KIND == kAdjCompensatedInline;
   // Neighbouring runs and all point groups of a run share G: keep them on
   // one XCD.
   const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
@@ -77,23 +81,47 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
 #pragma unroll
     for (int k = 0; k < kAdjCols; ++k) dst[k] = src[k];
   };
-  auto do_row = [&](int row, const float* gc, float* gn) {
-    const float yh = (float)row;
-    const float dy = yh - py;
+  // The compensated kind's {y-phase, dy} of a row, from the row table (one
+  // 8-byte load per lane, issued a row ahead like G).
+  // A buffer load: the row's byte offset (at most kAdjRowTabMaxBytes) is a
+  // scalar operand and the lane's offset a 32-bit vector one, so forming the
+  // address costs no vector instruction; the descriptor bounds the table.
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  const __amdgpu_buffer_rsrc_t rtab_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float2*>(rtab), 0, KIND == kAdjCompensated ? (int)((int64_t)ny * npad * 8) : 0,
+      0x00020000);
+  auto load_rtab = [&](int row) {
+    const f32x2 v = __builtin_bit_cast(
+        f32x2, __builtin_amdgcn_raw_buffer_load_b64(rtab_rsrc, (unsigned)j * 8u,
+                                                    (int)((int64_t)row * npad * 8), 0));
+    return make_float2(v.x, v.y);
+  };
+  auto do_row = [&](int row, const float* gc, float* gn, float2 rc, float2& rn) {
+    float dy, RY;
+    if (KIND == kAdjCompensated) {
+      RY = rc.x;
+      dy = rc.y;
+    } else {
+      const float yh = (float)row;
+      dy = yh - py;
+      RY = KIND == kAdjCompensatedInline ? axis_phase(yh, yc, yph, ypl, yb, yd) : 0.f;
+    }
     const float dy2 = dy * dy;
-    const float RY = KIND == kAdjCompensated ? axis_phase(yh, yc, yph, ypl, yb, yd) : dy2;
+    if (KIND == kAdjPlain) RY = dy2;
     float gam = KIND == kAdjRecurrence ? fract(prev * (dx0sq + dy2)) : 0.f;
     float sr0 = 0.f, sr1 = 0.f;
 #pragma unroll
     for (int c = 0; c < kAdjCols; ++c) {
       if (c == 1) {
         __builtin_amdgcn_sched_barrier(0);
-        load_row(min(row + 1, row1 - 1), gn);
+        const int next = min(row + 1, row1 - 1);
+        load_row(next, gn);
+        if (KIND == kAdjCompensated) rn = load_rtab(next);
         __builtin_amdgcn_sched_barrier(0);
       }
       const float G = gc[c];
       float t;
-      if (KIND == kAdjCompensated) {
+      if (kComp) {
         t = CX[c] + RY;
       } else if (KIND == kAdjRecurrence) {
         t = gam;
@@ -128,7 +156,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
 #pragma unroll
     for (int c = 0; c < kAdjCols; ++c) {
       const float h = (float)(col0 + c);
-      if (KIND == kAdjCompensated)
+      if (kComp)
         CX[c] = axis_phase(h, xc, xph, xpl, xb, xd);
       else if (KIND == kAdjRecurrence)
         CX[c] = fract(prev * __builtin_fmaf(2.0f, h - px, 1.0f));
@@ -141,13 +169,15 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
       dx0sq = dx0 * dx0;
     }
     float gA[kAdjCols], gB[kAdjCols];
+    float2 rA = make_float2(0.f, 0.f), rB = rA;
     load_row(row0, gA);
+    if (KIND == kAdjCompensated) rA = load_rtab(row0);
     int row = row0;
     for (; row + 1 < row1; row += 2) {
-      do_row(row, gA, gB);
-      do_row(row + 1, gB, gA);
+      do_row(row, gA, gB, rA, rB);
+      do_row(row + 1, gB, gA, rB, rA);
     }
-    if (row < row1) do_row(row, gA, gB);
+    if (row < row1) do_row(row, gA, gB, rA, rB);
 #pragma unroll
     for (int c = 0; c < kAdjCols; ++c) {
       const float dx = (float)(col0 + c) - px;
@@ -170,8 +200,24 @@ __global__ __launch_bounds__(kAdjFinPoints* kAdjFinSlices) void adj_finalize_ker
   const int64_t j = (int64_t)blockIdx.x * kAdjFinPoints + pt;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   if (j < npad) {
-    // Regions slice, slice + kAdjFinSlices, ... in increasing order.
-    for (int r = slice; r < regions; r += kAdjFinSlices) {
+    // Regions slice, slice + kAdjFinSlices, ... in increasing order.  The
+    // loads of kFinBatch regions are issued together, then added in order.
+    constexpr int kFinBatch = 8;
+    int r = slice;
+    for (; r + (kFinBatch - 1) * kAdjFinSlices < regions; r += kFinBatch * kAdjFinSlices) {
+      float4 v[kFinBatch];
+#pragma unroll
+      for (int q = 0; q < kFinBatch; ++q)
+        v[q] = partial[(int64_t)(r + q * kAdjFinSlices) * npad + j];
+#pragma unroll
+      for (int q = 0; q < kFinBatch; ++q) {
+        s0 += (double)v[q].x;
+        s1 += (double)v[q].y;
+        s2 += (double)v[q].z;
+        s3 += (double)v[q].w;
+      }
+    }
+    for (; r < regions; r += kAdjFinSlices) {
       const float4 v = partial[(int64_t)r * npad + j];
       s0 += (double)v.x;
       s1 += (double)v.y;
@@ -244,6 +290,9 @@ int adj_runs(const Plan& p) {
     if (p.adj_kind == kAdjCompensated)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &per_cu, adj_partial_kernel<kAdjCompensated>, kAdjThreads, 0);
+    else if (p.adj_kind == kAdjCompensatedInline)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, adj_partial_kernel<kAdjCompensatedInline>, kAdjThreads, 0);
     else if (p.adj_kind == kAdjRecurrence)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &per_cu, adj_partial_kernel<kAdjRecurrence>, kAdjThreads, 0);
@@ -266,10 +315,14 @@ hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* x,
   const dim3 grid(runs, p.ngroups);
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, grid, dim3(kAdjThreads), 0, s, x, y, z, a, p.n, pitch, wavelength,
-                       g, ldg, p.ny, p.strip_rows, (int)p.npad, (float4*)w.partial);
+                       g, ldg, p.ny, p.strip_rows, (int)p.npad, (const float2*)w.rtab,
+                       (float4*)w.partial);
   };
-  if (p.adj_kind == kAdjCompensated)
+  if (p.adj_kind == kAdjCompensated) {
+    if (!w.rtab) return hipErrorInvalidValue;
     go(adj_partial_kernel<kAdjCompensated>);
+  } else if (p.adj_kind == kAdjCompensatedInline)
+    go(adj_partial_kernel<kAdjCompensatedInline>);
   else if (p.adj_kind == kAdjRecurrence)
     go(adj_partial_kernel<kAdjRecurrence>);
   else

@@ -124,7 +124,9 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   p.rec_s = 2;
 #endif
   p.ngroups = (int32_t)(p.npad / kWave);
-  p.adj_kind = variant == CGH_COMPENSATED  ? kAdjCompensated
+  const bool rtab_fits =
+      (int64_t)ny * p.npad <= kAdjRowTabMaxBytes / (int64_t)sizeof(float2);
+  p.adj_kind = variant == CGH_COMPENSATED  ? (rtab_fits ? kAdjCompensated : kAdjCompensatedInline)
                : variant == CGH_RECURRENCE ? kAdjRecurrence
                                            : kAdjPlain;
   p.nsx = (int32_t)ceil_div(nx, kAdjCols);
@@ -160,6 +162,9 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
                    ? take((size_t)p.groups * np * kCompRows * sizeof(float))
                    : 0;
   const bool direct_adj = op == CGH_OP_BACKWARD && !is_separable(variant);
+  p.off_rtab = (direct_adj && p.adj_kind == kAdjCompensated)
+                   ? take((size_t)ny * np * sizeof(float2))
+                   : 0;
   p.off_partial = direct_adj ? take((size_t)p.regions * np * sizeof(float4)) : 0;
   p.off_gpad = (direct_adj && p.need_gpad)
                    ? take((size_t)p.nsx * kAdjCols * (size_t)ny * sizeof(float))
@@ -203,6 +208,7 @@ Workspace carve(const Plan& p, void* base) {
   w.ytab = (p.op == CGH_OP_FORWARD && p.variant == CGH_COMPENSATED) ? (float*)(b + p.off_ytab)
                                                                      : nullptr;
   const bool direct_adj = p.op == CGH_OP_BACKWARD && !is_separable(p.variant);
+  w.rtab = (direct_adj && p.adj_kind == kAdjCompensated) ? (float2*)(b + p.off_rtab) : nullptr;
   w.partial = direct_adj ? (float*)(b + p.off_partial) : nullptr;
   w.gpad = (direct_adj && p.need_gpad) ? (float*)(b + p.off_gpad) : nullptr;
   const bool sep = is_separable(p.variant) && p.op != CGH_OP_FORWARD_F64;
@@ -509,7 +515,11 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
                                    grad_z, grad_a, s);
   }
   // The direct adjoint forms each point's records itself (one point per
-  // lane), so it needs no precompute launch.
+  // lane); the compensated one takes its row phases from a table built here.
+  if (p.adj_kind == kAdjCompensated) {
+    e = launch_prep_rtab(x, y, z, a, pitch, wavelength, p, w, s);
+    if (e != hipSuccess) return CGH_EHIP;
+  }
   const float* g = grad_hologram;
   int64_t ldg = nx;
   if (p.need_gpad) {

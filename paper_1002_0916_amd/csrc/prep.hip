@@ -1,6 +1,7 @@
-// Per-point precompute (FP64 arithmetic, O(N)), the per-row phase table of
-// the compensated forward (fused with the precompute), and small fill
-// kernels.  The records themselves are defined in records.h.
+// Per-point precompute (FP64 arithmetic, O(N)), the per-row phase tables of
+// the compensated forward (fused with the precompute) and of the compensated
+// adjoint, and small fill kernels.  The records themselves are defined in
+// records.h.
 #include "cgh_internal.h"
 #include "phase.h"
 #include "records.h"
@@ -76,6 +77,28 @@ __global__ __launch_bounds__(256) void prep_ytab_kernel(
     dst[i] = axis_phase((float)(g * kCompRows + i), r.yc, r.ph, r.pl, r.yb, r.yd);
 }
 
+// The compensated adjoint's row table: thread (g, j) forms point j's records
+// and writes, for the kRtabRows rows y_h of row group g,
+//   rtab[y_h][j] = {axis_phase(y_h) of point j, y_h - y_j},
+// the two values the adjoint kernel would otherwise form per strip.
+constexpr int kRtabRows = 8;
+__global__ __launch_bounds__(256) void prep_rtab_kernel(
+    const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
+    const float* __restrict__ a, int64_t n, int64_t npad, int ny, int64_t groups, double pitch,
+    double wavelength, float2* __restrict__ rtab) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= groups * npad) return;
+  const int64_t g = t / npad, j = t - g * npad;
+  const PointRecord r = point_record(x, y, z, a, j, n, pitch, wavelength);
+  const int row0 = (int)(g * kRtabRows);
+  const int rows = min(kRtabRows, ny - row0);
+  for (int i = 0; i < rows; ++i) {
+    const float yh = (float)(row0 + i);
+    rtab[(int64_t)(row0 + i) * npad + j] =
+        make_float2(axis_phase(yh, r.yc, r.ph, r.pl, r.yb, r.yd), yh - r.y);
+  }
+}
+
 __global__ __launch_bounds__(256) void zero_f32_kernel(float* __restrict__ p, int64_t count) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < count) p[t] = 0.0f;
@@ -106,6 +129,17 @@ hipError_t launch_prep_ytab(const float* x, const float* y, const float* z, cons
   hipLaunchKernelGGL(prep_ytab_kernel, dim3(blocks), dim3(256), 0, s, x, y, z, a,
                      p.n, p.npad, (int64_t)p.groups, pitch, wavelength, w.plain, w.amp, w.xrec,
                      w.yrec, w.ytab);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_rtab(const float* x, const float* y, const float* z, const float* a,
+                            double pitch, double wavelength, const Plan& p, const Workspace& w,
+                            hipStream_t s) {
+  const int64_t groups = (p.ny + kRtabRows - 1) / kRtabRows;
+  const unsigned blocks = grid_blocks(groups * p.npad, 256);
+  if (!blocks || !w.rtab) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(prep_rtab_kernel, dim3(blocks), dim3(256), 0, s, x, y, z, a, p.n, p.npad,
+                     p.ny, groups, pitch, wavelength, w.rtab);
   return hipGetLastError();
 }
 

@@ -105,13 +105,39 @@ __global__ __launch_bounds__(kWave* kFinSlices) void sep_finalize_kernel(
   const int64_t j = (int64_t)blockIdx.x * kWave + lane;
   double Sc = 0.0, Sx = 0.0, Srx = 0.0, Sy = 0.0, Sry = 0.0;
   if (j < npad) {
-    for (int k = slice; k < planes_x; k += kFinSlices) {
+    // Planes slice, slice + kFinSlices, ... in increasing order; the loads of
+    // kFinBatch planes are issued together, then added in order.
+    constexpr int kFinBatch = 4;
+    int k = slice;
+    for (; k + (kFinBatch - 1) * kFinSlices < planes_x; k += kFinBatch * kFinSlices) {
+      float4 v[kFinBatch];
+#pragma unroll
+      for (int q = 0; q < kFinBatch; ++q) v[q] = fold_x[(int64_t)(k + q * kFinSlices) * npad + j];
+#pragma unroll
+      for (int q = 0; q < kFinBatch; ++q) {
+        Sc += (double)v[q].x;
+        Sx += (double)v[q].y;
+        Srx += (double)v[q].z;
+      }
+    }
+    for (; k < planes_x; k += kFinSlices) {
       const float4 v = fold_x[(int64_t)k * npad + j];
       Sc += (double)v.x;
       Sx += (double)v.y;
       Srx += (double)v.z;
     }
-    for (int k = slice; k < planes_y; k += kFinSlices) {
+    k = slice;
+    for (; k + (kFinBatch - 1) * kFinSlices < planes_y; k += kFinBatch * kFinSlices) {
+      float4 v[kFinBatch];
+#pragma unroll
+      for (int q = 0; q < kFinBatch; ++q) v[q] = fold_y[(int64_t)(k + q * kFinSlices) * npad + j];
+#pragma unroll
+      for (int q = 0; q < kFinBatch; ++q) {
+        Sy += (double)v[q].y;
+        Sry += (double)v[q].z;
+      }
+    }
+    for (; k < planes_y; k += kFinSlices) {
       const float4 v = fold_y[(int64_t)k * npad + j];
       Sy += (double)v.y;
       Sry += (double)v.z;

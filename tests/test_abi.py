@@ -98,6 +98,16 @@ def test_workspace_bytes(lib):
     assert 0 < p < c and p < d and p < b
     # the per-row phase table of the compensated forward: >= N * Ny floats
     assert c - p >= 1024 * 1024 * 4
+    # the compensated adjoint's row table, {y-phase, dy} per row and point,
+    # is N * Ny float2 while that fits in 512 MiB; above it the kernel forms
+    # the values itself and the workspace equals the plain adjoint's
+    bp = f(1024, 1920, 1024, B.PLAIN, B.OP_BACKWARD)
+    assert b - bp == 1024 * 1024 * 8
+    big = (16448, 32, 4096)
+    assert big[0] * big[2] * 8 > 512 << 20
+    assert f(*big, B.COMPENSATED, B.OP_BACKWARD) == f(*big, B.PLAIN, B.OP_BACKWARD)
+    edge = (4096, 32, 16384)  # exactly 512 MiB: still a table
+    assert f(*edge, B.COMPENSATED, B.OP_BACKWARD) - f(*edge, B.PLAIN, B.OP_BACKWARD) == 512 << 20
     for v in (p, c, d, b):
         assert v % 256 == 0
     # monotone in N

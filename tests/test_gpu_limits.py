@@ -116,6 +116,29 @@ def test_longest_side(oracle_mod, variant, shape):
     _compare_grads([v[idx] for v in gg], ref, variant)
 
 
+def test_compensated_adjoint_without_row_table(oracle_mod):
+    """4096 rows x 16448 points: the compensated adjoint's row table would take
+    more than its 512 MiB bound, so the kernel forms the row phases itself
+    (the inline form of the same arithmetic).  The points stay inside the
+    grid, within the 4096 pixels of exact-grid arithmetic of every pixel."""
+    nx, ny, n = 32, 4096, 16448
+    assert ny * n * 8 > 512 << 20
+    assert (B.workspace_bytes(n, nx, ny, "compensated", B.OP_BACKWARD)
+            == B.workspace_bytes(n, nx, ny, "plain", B.OP_BACKWARD))
+    dev = device()
+    say("limits: compensated adjoint without the row table, %dx%d, n = %d" % (nx, ny, n))
+    c = W.random_cloud(430, n, nx, ny, zlo=0.5, zhi=1.0, alo=-1.0, ahi=1.0)
+    rng = np.random.default_rng(431)
+    G = rng.standard_normal((ny, nx)).astype(np.float32)
+    idx = np.sort(rng.choice(n, size=24, replace=False))
+    x, y, z, a = to_dev(c, dev)
+    g = torch.from_numpy(G).to(dev)
+    gg = [t[torch.from_numpy(idx).to(dev)].cpu().numpy()
+          for t in B.backward(x, y, z, a, g, nx, ny, variant="compensated")]
+    ref = oracle_mod.adjoint(*c.astuple(), nx, ny, G, idx=idx, threads=0)
+    _compare_grads(gg, ref, "compensated")
+
+
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_more_than_2_31_pixels(oracle_mod, variant):
     """65536 x 32769 = 2,147,549,184 pixels (> 2^31): forward on sampled
