@@ -112,6 +112,7 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   p.fwd_gy = (int32_t)ceil_div(ny, kFwdRowsPerWG);
   p.comp_gy = (int32_t)ceil_div(ny, kCompRowsPerWG);
   p.groups = p.comp_gy * kCompWaves;
+  p.comp_xtab = (int64_t)p.fwd_gx * kWave * p.npad <= kCompColTabMaxBytes / (int64_t)sizeof(float);
   rec_shape(nx, ny, p.rec_k, p.rec_r);
   p.rec_gx = (int32_t)ceil_div(nx, (int64_t)kWave * p.rec_k);
   p.rec_gy = (int32_t)ceil_div(ny, (int64_t)kRecWaves * p.rec_r);
@@ -161,6 +162,9 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   p.off_ytab = (op == CGH_OP_FORWARD && variant == CGH_COMPENSATED)
                    ? take((size_t)p.groups * np * kCompRows * sizeof(float))
                    : 0;
+  p.off_xtab = (op == CGH_OP_FORWARD && variant == CGH_COMPENSATED && p.comp_xtab)
+                   ? take((size_t)p.fwd_gx * kWave * np * sizeof(float))
+                   : 0;
   const bool direct_adj = op == CGH_OP_BACKWARD && !is_separable(variant);
   p.off_rtab = (direct_adj && p.adj_kind == kAdjCompensated)
                    ? take((size_t)ny * np * sizeof(float2))
@@ -207,6 +211,9 @@ Workspace carve(const Plan& p, void* base) {
   w.rec64 = p.op == CGH_OP_FORWARD_F64 ? (double4*)(b + p.off_rec64) : nullptr;
   w.ytab = (p.op == CGH_OP_FORWARD && p.variant == CGH_COMPENSATED) ? (float*)(b + p.off_ytab)
                                                                      : nullptr;
+  w.xtab = (p.op == CGH_OP_FORWARD && p.variant == CGH_COMPENSATED && p.comp_xtab)
+               ? (float*)(b + p.off_xtab)
+               : nullptr;
   const bool direct_adj = p.op == CGH_OP_BACKWARD && !is_separable(p.variant);
   w.rtab = (direct_adj && p.adj_kind == kAdjCompensated) ? (float2*)(b + p.off_rtab) : nullptr;
   w.partial = direct_adj ? (float*)(b + p.off_partial) : nullptr;

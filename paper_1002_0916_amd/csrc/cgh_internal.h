@@ -71,6 +71,10 @@ constexpr int kCompThreads = kCompWaves * kWave;
 constexpr int kCompRowsPerWG = kCompWaves * kCompRows;
 static_assert(kWave % kCompWaves == 0, "x-phase fill splits the 64 columns over the waves");
 static_assert(kTile % (2 * kCompUnroll) == 0, "tiles hold whole ping-pong group pairs");
+// The compensated forward reads its x-phases from a column table
+// [fwd_gx * 64][npad] while that takes at most kCompColTabMaxBytes, else it
+// forms them per workgroup (the same values).
+constexpr int64_t kCompColTabMaxBytes = int64_t(512) << 20;
 constexpr int kPointPad = 64;
 
 // Recurrence forward (Eq. (2)): lane l of a wave covers K consecutive pixels
@@ -144,6 +148,7 @@ struct Workspace {
   float* yrec;     // [npad][8]
   double4* rec64;  // [npad]
   float* ytab;     // forward, compensated: [groups][npad][kCompRows]
+  float* xtab;     // forward, compensated (optional): [fwd_gx * 64][npad] x-phases
   float2* rtab;    // adjoint, compensated: [ny][npad] {y-phase, y_h - y_j}
   float* partial;  // adjoint: [regions][npad][4]
   float* gpad;     // adjoint: G copied to a [ny][nsx*kAdjCols] zero-padded grid
@@ -168,6 +173,7 @@ struct Plan {
   int32_t variant, op;
   // forward
   int32_t fwd_gx, fwd_gy, comp_gy, groups;
+  bool comp_xtab;  // the compensated forward has its column table
   int32_t rec_k, rec_r, rec_s, rec_gx, rec_gy;  // recurrence forward shape, split, grid
   // adjoint: runs of strip-rows per point group (regions = the most runs the
   // partial buffer holds; the launch may use fewer)
@@ -179,8 +185,8 @@ struct Plan {
   int64_t k2;
   size_t off_sep_x, off_sep_y, off_sep_c, off_sep_g, off_fold_x, off_fold_y;
   size_t off_hx, off_hy, off_hg, off_hgt, off_hmax;  // half variants (hi plane; lo follows)
-  size_t off_plain, off_amp, off_xrec, off_yrec, off_rec64, off_ytab, off_rtab, off_partial,
-      off_gpad, total;
+  size_t off_plain, off_amp, off_xrec, off_yrec, off_rec64, off_ytab, off_xtab, off_rtab,
+      off_partial, off_gpad, total;
 };
 
 Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op);
@@ -194,8 +200,9 @@ hipError_t launch_prep(const float* x, const float* y, const float* z, const flo
                        bool want64, hipStream_t s);
 hipError_t launch_fill_zero_f32(float* p, int64_t count, hipStream_t s);
 hipError_t launch_fill_zero_f64(double* p, int64_t count, hipStream_t s);
-// The compensated forward's precompute: the point records (as launch_prep)
-// and the per-row y-phase table, in one launch.
+// The compensated forward's precompute: the point records (as launch_prep),
+// the per-row y-phase table and (when planned) the column x-phase table, in
+// one launch.
 hipError_t launch_prep_ytab(const float* x, const float* y, const float* z, const float* a,
                             double pitch, double wavelength, const Plan& p, const Workspace& w,
                             hipStream_t s);

@@ -182,19 +182,24 @@ __global__ __launch_bounds__(kRecThreads * S) void fwd_rec_kernel(const float4* 
 // X_j(x_h) = Prev (x_h - x_j)^2 and Y_j(y_h) = Prev (y_h - y_j)^2.  Each part
 // is formed on the integer pixel grid as a compensated split product reduced
 // mod 1 (axis_phase).  Y comes from the per-row table (wave-uniform, scalar
-// loads).  X depends on the column and the point only, and the four waves of
-// a workgroup share their 64 columns, so the workgroup computes X once per
-// tile of kTile points into LDS, double buffered so that filling tile t+1
+// loads).  X depends on the column and the point only, and the kCompWaves
+// waves of a workgroup share their 64 columns, so the workgroup stages X for
+// a tile of kTile points in LDS, double buffered so that filling tile t+1
 // overlaps consuming tile t.  For the fill, lane l holds point l of the tile
-// (its record arrives by one coalesced vector load, issued a tile ahead) and
-// wave w computes the 16 columns 16w..16w+15.  Per interaction: one LDS-fed
-// add, the native cosine (no fract: the sum stays within a few revolutions)
-// and one fma.
-__global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(const float* __restrict__ xrec,
-                                                               const float* __restrict__ amp,
-                                                               const float* __restrict__ ytab,
-                                                               int npad, int nx, int ny,
-                                                               float* __restrict__ out) {
+// and wave w the kWave / kCompWaves columns from w kWave / kCompWaves on.
+// With TAB the values come from the column table xtab[col][npad] (built with
+// the row table; buffer loads issued a tile before their LDS store, no
+// arithmetic), else each lane forms them from its point's record (a vector
+// load issued a tile ahead).
+// Either way they are the same bits.  Per interaction: one LDS-fed add, the
+// native cosine (no fract: the sum stays within a few revolutions) and one
+// fma.
+template <bool TAB>
+__device__ __forceinline__ void fwd_comp_body(const float* __restrict__ xrec,
+                                              const float* __restrict__ xtab,
+                                              const float* __restrict__ amp,
+                                              const float* __restrict__ ytab, int npad, int nx,
+                                              int ny, float* __restrict__ out) {
   __shared__ float xs[2][kTile * kTilePitch];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -208,11 +213,27 @@ __global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(const float* __r
   const int ntiles = npad / kTile;
   constexpr int kColsPerWave = kWave / kCompWaves;
 
-  // This lane's point record {c, Ph, Pl, b, d} for the tile being filled.
+  // This lane's point record {c, Ph, Pl, b, d} for the tile being filled
+  // (inline form), or the tile's column values (table form: the column's
+  // byte offset is a scalar operand of a buffer load, the lane's a vector
+  // one; the descriptor spans the table, gridDim.x * 64 columns of npad).
   auto load_rec = [&](int tile, float4& r0, float& r1) {
     const float* r = xrec + (int64_t)(tile * kTile + lane) * kAxisRec;
     r0 = *reinterpret_cast<const float4*>(r);
     r1 = r[4];
+  };
+  const __amdgpu_buffer_rsrc_t xtab_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(xtab), 0, TAB ? (int)((int64_t)gridDim.x * kWave * npad * 4) : 0,
+      0x00020000);
+  auto load_cols = [&](int tile, float* xv) {
+#pragma unroll
+    for (int k = 0; k < kColsPerWave; ++k) {
+      const int c = col0 + wave * kColsPerWave + k;
+      xv[k] = __builtin_bit_cast(
+          float, __builtin_amdgcn_raw_buffer_load_b32(
+                     xtab_rsrc, (unsigned)lane * 4u,
+                     (int)(((int64_t)c * npad + (int64_t)tile * kTile) * 4), 0));
+    }
   };
   auto fill = [&](int buf, const float4& r0, float r1) {
 #pragma unroll
@@ -220,6 +241,11 @@ __global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(const float* __r
       const int c = wave * kColsPerWave + k;
       xs[buf][lane * kTilePitch + c] = axis_phase((float)(col0 + c), r0.x, r0.y, r0.z, r0.w, r1);
     }
+  };
+  auto store_cols = [&](int buf, const float* xv) {
+#pragma unroll
+    for (int k = 0; k < kColsPerWave; ++k)
+      xs[buf][lane * kTilePitch + wave * kColsPerWave + k] = xv[k];
   };
   // Row phases and amplitudes of kCompUnroll consecutive points, read
   // through scalar loads (SGPRs) and software-pipelined one group ahead: the
@@ -259,15 +285,27 @@ __global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(const float* __r
   float yA[kCompUnroll * kCompRows], aA[kCompUnroll], yB[kCompUnroll * kCompRows], aB[kCompUnroll];
   float4 r0;
   float r1;
-  load_rec(0, r0, r1);
-  fill(0, r0, r1);
-  if (ntiles > 1) load_rec(1, r0, r1);
+  float xv[kColsPerWave];
+  if (TAB) {
+    load_cols(0, xv);
+    store_cols(0, xv);
+    if (ntiles > 1) load_cols(1, xv);
+  } else {
+    load_rec(0, r0, r1);
+    fill(0, r0, r1);
+    if (ntiles > 1) load_rec(1, r0, r1);
+  }
   load_group(0, yA, aA);
   __syncthreads();
   for (int t = 0; t < ntiles; ++t) {
     if (t + 1 < ntiles) {
-      fill((t + 1) & 1, r0, r1);
-      if (t + 2 < ntiles) load_rec(t + 2, r0, r1);
+      if (TAB) {
+        store_cols((t + 1) & 1, xv);
+        if (t + 2 < ntiles) load_cols(t + 2, xv);
+      } else {
+        fill((t + 1) & 1, r0, r1);
+        if (t + 2 < ntiles) load_rec(t + 2, r0, r1);
+      }
     }
     const float* xt = xs[t & 1];
     for (int p = 0; p < kTile; p += 2 * kCompUnroll) {
@@ -282,6 +320,20 @@ __global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(const float* __r
     for (int i = 0; i < kCompRows; ++i)
       if (y0 + i < ny) out[(int64_t)(y0 + i) * nx + col] = acc[i];
   }
+}
+
+__global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(const float* __restrict__ xtab,
+                                                               const float* __restrict__ amp,
+                                                               const float* __restrict__ ytab,
+                                                               int npad, int nx, int ny,
+                                                               float* __restrict__ out) {
+  fwd_comp_body<true>(nullptr, xtab, amp, ytab, npad, nx, ny, out);
+}
+
+__global__ __launch_bounds__(kCompThreads) void fwd_comp_inline_kernel(
+    const float* __restrict__ xrec, const float* __restrict__ amp, const float* __restrict__ ytab,
+    int npad, int nx, int ny, float* __restrict__ out) {
+  fwd_comp_body<false>(xrec, nullptr, amp, ytab, npad, nx, ny, out);
 }
 
 // FP64 reference: rho = Prev ((x_h - x_j)^2 + (y_h - y_j)^2) in revolutions,
@@ -344,9 +396,14 @@ hipError_t launch_fwd_rec(const Plan& p, const Workspace& w, float* out, hipStre
 }
 
 hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(fwd_comp_kernel, dim3(p.fwd_gx, p.comp_gy), dim3(kCompThreads), 0, s,
-                     (const float*)w.xrec, (const float*)w.amp, (const float*)w.ytab, (int)p.npad,
-                     p.nx, p.ny, out);
+  if (w.xtab)
+    hipLaunchKernelGGL(fwd_comp_kernel, dim3(p.fwd_gx, p.comp_gy), dim3(kCompThreads), 0, s,
+                       (const float*)w.xtab, (const float*)w.amp, (const float*)w.ytab,
+                       (int)p.npad, p.nx, p.ny, out);
+  else
+    hipLaunchKernelGGL(fwd_comp_inline_kernel, dim3(p.fwd_gx, p.comp_gy), dim3(kCompThreads), 0,
+                       s, (const float*)w.xrec, (const float*)w.amp, (const float*)w.ytab,
+                       (int)p.npad, p.nx, p.ny, out);
   return hipGetLastError();
 }
 

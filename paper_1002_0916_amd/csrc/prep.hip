@@ -57,24 +57,36 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ x,
                 rec64);
 }
 
-// The compensated forward's precompute in one launch: thread (g, j) forms
-// point j's records, writes them when g = 0, and writes the y-axis phases of
-// point j at the kCompRows rows of row group g:
+// The compensated forward's precompute in one launch.  Thread (g, j) with
+// g < groups forms point j's records, writes them when g = 0, and writes the
+// y-axis phases of point j at the kCompRows rows of row group g:
 //   ytab[g][j][i] = axis_phase(g * kCompRows + i) of point j.
+// The threads after those (when xtab is given) write the x-axis phases of
+// point j at the kXtabCols columns of column group g - groups:
+//   xtab[col][j] = axis_phase(col) of point j.
+constexpr int kXtabCols = 8;
 __global__ __launch_bounds__(256) void prep_ytab_kernel(
     const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
-    const float* __restrict__ a, int64_t n, int64_t npad, int64_t groups, double pitch,
-    double wavelength, float4* __restrict__ plain, float* __restrict__ amp,
-    float* __restrict__ xrec, float* __restrict__ yrec, float* __restrict__ ytab) {
+    const float* __restrict__ a, int64_t n, int64_t npad, int64_t groups, int64_t xgroups,
+    double pitch, double wavelength, float4* __restrict__ plain, float* __restrict__ amp,
+    float* __restrict__ xrec, float* __restrict__ yrec, float* __restrict__ ytab,
+    float* __restrict__ xtab) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= groups * npad) return;
+  if (t >= (groups + xgroups) * npad) return;
   const int64_t g = t / npad, j = t - g * npad;
   const PointRecord r = point_record(x, y, z, a, j, n, pitch, wavelength);
-  if (g == 0) store_records(r, j, plain, amp, xrec, yrec, nullptr);
-  float* dst = ytab + t * kCompRows;
+  if (g < groups) {
+    if (g == 0) store_records(r, j, plain, amp, xrec, yrec, nullptr);
+    float* dst = ytab + t * kCompRows;
 #pragma unroll
-  for (int i = 0; i < kCompRows; ++i)
-    dst[i] = axis_phase((float)(g * kCompRows + i), r.yc, r.ph, r.pl, r.yb, r.yd);
+    for (int i = 0; i < kCompRows; ++i)
+      dst[i] = axis_phase((float)(g * kCompRows + i), r.yc, r.ph, r.pl, r.yb, r.yd);
+  } else {
+    const int64_t c0 = (g - groups) * kXtabCols;
+#pragma unroll
+    for (int k = 0; k < kXtabCols; ++k)
+      xtab[(c0 + k) * npad + j] = axis_phase((float)(c0 + k), r.xc, r.ph, r.pl, r.xb, r.xd);
+  }
 }
 
 // The compensated adjoint's row table: thread (g, j) forms point j's records
@@ -123,12 +135,14 @@ hipError_t launch_prep(const float* x, const float* y, const float* z, const flo
 hipError_t launch_prep_ytab(const float* x, const float* y, const float* z, const float* a,
                             double pitch, double wavelength, const Plan& p, const Workspace& w,
                             hipStream_t s) {
-  const int64_t total = (int64_t)p.groups * p.npad;
+  static_assert(kWave % kXtabCols == 0, "column groups tile the forward's 64-column blocks");
+  const int64_t xgroups = w.xtab ? (int64_t)p.fwd_gx * kWave / kXtabCols : 0;
+  const int64_t total = ((int64_t)p.groups + xgroups) * p.npad;
   const unsigned blocks = grid_blocks(total, 256);
   if (!blocks) return hipErrorInvalidValue;
   hipLaunchKernelGGL(prep_ytab_kernel, dim3(blocks), dim3(256), 0, s, x, y, z, a,
-                     p.n, p.npad, (int64_t)p.groups, pitch, wavelength, w.plain, w.amp, w.xrec,
-                     w.yrec, w.ytab);
+                     p.n, p.npad, (int64_t)p.groups, xgroups, pitch, wavelength, w.plain, w.amp,
+                     w.xrec, w.yrec, w.ytab, w.xtab);
   return hipGetLastError();
 }
 

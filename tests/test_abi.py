@@ -96,8 +96,14 @@ def test_workspace_bytes(lib):
     d = f(1024, 1920, 1024, B.PLAIN, B.OP_FORWARD_F64)
     b = f(1024, 1920, 1024, B.COMPENSATED, B.OP_BACKWARD)
     assert 0 < p < c and p < d and p < b
-    # the per-row phase table of the compensated forward: >= N * Ny floats
-    assert c - p >= 1024 * 1024 * 4
+    # the compensated forward's tables: row phases [256 row groups][N][4] and
+    # column phases [30 * 64 columns][N]
+    assert c - p == 256 * 1024 * 4 * 4 + 30 * 64 * 1024 * 4
+    # the column table is dropped above 512 MiB (64 columns x 4M points)
+    big_f = (4000000, 64, 16)
+    row_tab = 8 * 4000000 * 4 * 4  # 8 row groups of 4 rows
+    assert (f(*big_f, B.COMPENSATED, B.OP_FORWARD) - f(*big_f, B.PLAIN, B.OP_FORWARD)
+            == row_tab)
     # the compensated adjoint's row table, {y-phase, dy} per row and point,
     # is N * Ny float2 while that fits in 512 MiB; above it the kernel forms
     # the values itself and the workspace equals the plain adjoint's
