@@ -823,11 +823,15 @@ def summarize_stats(root):
 # the algorithmic bytes of one launch at the headline workload.
 TRAFFIC_KERNELS = {
     "adj_partial_kernel<1>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"],
+                              "G 7.86 MB + row table 8.39 MB (read once per strip: 60x) + "
+                              "inputs 0.02 MB + run partials 8.39 MB (512 runs)"),
+    "adj_partial_kernel<0>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"],
                               "G 7.86 MB + inputs 0.02 MB + run partials 8.39 MB (512 runs)"),
-    "adj_partial_kernel<0>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"], "same"),
-    "adj_partial_kernel<2>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"], "same"),
+    "adj_partial_kernel<2>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"],
+                              "G 7.86 MB + inputs 0.02 MB + run partials 8.39 MB (512 runs)"),
     "fwd_comp_kernel": (["forward.hip", "phase.h", "cgh_internal.h"],
-                        "row table 4.19 MB + records 0.05 MB + hologram 7.86 MB"),
+                        "row table 4.19 MB + column table 7.86 MB (read once per row block: "
+                        "32x) + amplitudes + hologram 7.86 MB"),
     "fwd_plain_kernel": (["forward.hip", "phase.h", "cgh_internal.h"],
                          "records 0.02 MB + hologram 7.86 MB"),
     "fwd_rec_kernel<8, 4, 2>": (["forward.hip", "phase.h", "cgh_internal.h"],

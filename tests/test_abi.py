@@ -99,11 +99,20 @@ def test_workspace_bytes(lib):
     # the compensated forward's tables: row phases [256 row groups][N][4] and
     # column phases [30 * 64 columns][N]
     assert c - p == 256 * 1024 * 4 * 4 + 30 * 64 * 1024 * 4
-    # the column table is dropped above 512 MiB (64 columns x 4M points)
+    # the column table is dropped above 256 MiB (64 columns x 4M points)
     big_f = (4000000, 64, 16)
     row_tab = 8 * 4000000 * 4 * 4  # 8 row groups of 4 rows
     assert (f(*big_f, B.COMPENSATED, B.OP_FORWARD) - f(*big_f, B.PLAIN, B.OP_FORWARD)
             == row_tab)
+    # 1920 columns x 65536 points (503 MB): no column table; 3840 x 16384
+    # (252 MB): a column table
+    mesh = (65536, 1920, 1080)
+    rows_mesh = 34 * 8 * 65536 * 4 * 4
+    assert f(*mesh, B.COMPENSATED, B.OP_FORWARD) - f(*mesh, B.PLAIN, B.OP_FORWARD) == rows_mesh
+    fit = (16384, 3840, 2160)
+    rows_fit = 68 * 8 * 16384 * 4 * 4
+    assert (f(*fit, B.COMPENSATED, B.OP_FORWARD) - f(*fit, B.PLAIN, B.OP_FORWARD)
+            == rows_fit + 3840 * 16384 * 4)
     # the compensated adjoint's row table, {y-phase, dy} per row and point,
     # is N * Ny float2 while that fits in 512 MiB; above it the kernel forms
     # the values itself and the workspace equals the plain adjoint's
