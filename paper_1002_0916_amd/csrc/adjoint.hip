@@ -16,8 +16,10 @@
 // the recurrence steps) and the column sums of G sin(theta) in registers, and
 // per row it takes the row phase (or dy^2) once and folds the row sum of
 // G sin(theta) with dy and dy^2.  The compensated kind reads the row phase
-// and dy from a table built once per call (one 8-byte load per row and lane)
-// instead of forming them in every strip.
+// and dy from a row table (one 8-byte load per row and lane) and the strip's
+// column phases from a column table (one 4-byte load per column and lane per
+// strip segment), both built once per call, instead of forming them in every
+// strip.
 // Per interaction that leaves the phase, sin and cos, and three fused
 // multiply-adds with G taken straight from an SGPR.
 //
@@ -37,8 +39,9 @@ namespace cgh {
 
 namespace {
 
-// KIND: kAdjPlain, kAdjCompensated (row phases and dy from the row table),
-// kAdjCompensatedInline (the same values formed here) or kAdjRecurrence.  With the recurrence
+// KIND: kAdjPlain, kAdjCompensated (row phases and dy from the row table,
+// column phases from the column table), kAdjCompensatedInline (the same
+// values formed here) or kAdjRecurrence.  With the recurrence
 // (Eq. (2), Section 2.1) each strip row starts from the plain phase
 // Gamma_0 = fract(Prev r^2) at the strip's first column and steps
 // Gamma += delta_c, delta_c = Prev (2 (x_c - x_j) + 1) reduced mod 1, the
@@ -49,7 +52,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
     const float* __restrict__ a, int64_t n, double pitch, double wavelength,
     const float* __restrict__ g, int64_t ldg, int ny, int64_t strip_rows, int npad,
-    const float2* __restrict__ rtab, float4* __restrict__ partial) {
+    const float2* __restrict__ rtab, const float* __restrict__ ctab,
+    float4* __restrict__ partial) {
   constexpr bool kComp = KIND == kAdjCompensated || KIND == kAdjCompensatedInline;
   // Neighbouring runs and all point groups of a run share G: keep them on
   // one XCD.
@@ -89,6 +93,12 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
   typedef float f32x2 __attribute__((ext_vector_type(2)));
   const __amdgpu_buffer_rsrc_t rtab_rsrc = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float2*>(rtab), 0, KIND == kAdjCompensated ? (int)((int64_t)ny * npad * 8) : 0,
+      0x00020000);
+  // The compensated kind's column phases of a strip, from the column table
+  // [nsx * kAdjCols][npad] (one 4-byte buffer load per column and lane).
+  const __amdgpu_buffer_rsrc_t ctab_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(ctab), 0,
+      KIND == kAdjCompensated ? (int)((int64_t)(strip_rows / ny) * kAdjCols * npad * 4) : 0,
       0x00020000);
   auto load_rtab = [&](int row) {
     const f32x2 v = __builtin_bit_cast(
@@ -156,7 +166,11 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
 #pragma unroll
     for (int c = 0; c < kAdjCols; ++c) {
       const float h = (float)(col0 + c);
-      if (kComp)
+      if (KIND == kAdjCompensated)
+        CX[c] = __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(
+                       ctab_rsrc, (unsigned)j * 4u, (int)((int64_t)(col0 + c) * npad * 4), 0));
+      else if (kComp)
         CX[c] = axis_phase(h, xc, xph, xpl, xb, xd);
       else if (KIND == kAdjRecurrence)
         CX[c] = fract(prev * __builtin_fmaf(2.0f, h - px, 1.0f));
@@ -316,10 +330,10 @@ hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* x,
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, grid, dim3(kAdjThreads), 0, s, x, y, z, a, p.n, pitch, wavelength,
                        g, ldg, p.ny, p.strip_rows, (int)p.npad, (const float2*)w.rtab,
-                       (float4*)w.partial);
+                       (const float*)w.ctab, (float4*)w.partial);
   };
   if (p.adj_kind == kAdjCompensated) {
-    if (!w.rtab) return hipErrorInvalidValue;
+    if (!w.rtab || !w.ctab) return hipErrorInvalidValue;
     go(adj_partial_kernel<kAdjCompensated>);
   } else if (p.adj_kind == kAdjCompensatedInline)
     go(adj_partial_kernel<kAdjCompensatedInline>);

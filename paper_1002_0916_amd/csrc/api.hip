@@ -126,7 +126,8 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
 #endif
   p.ngroups = (int32_t)(p.npad / kWave);
   const bool rtab_fits =
-      (int64_t)ny * p.npad <= kAdjRowTabMaxBytes / (int64_t)sizeof(float2);
+      (int64_t)ny * p.npad <= kAdjRowTabMaxBytes / (int64_t)sizeof(float2) &&
+      ceil_div(nx, kAdjCols) * kAdjCols * p.npad <= kAdjRowTabMaxBytes / (int64_t)sizeof(float);
   p.adj_kind = variant == CGH_COMPENSATED  ? (rtab_fits ? kAdjCompensated : kAdjCompensatedInline)
                : variant == CGH_RECURRENCE ? kAdjRecurrence
                                            : kAdjPlain;
@@ -168,6 +169,9 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   const bool direct_adj = op == CGH_OP_BACKWARD && !is_separable(variant);
   p.off_rtab = (direct_adj && p.adj_kind == kAdjCompensated)
                    ? take((size_t)ny * np * sizeof(float2))
+                   : 0;
+  p.off_ctab = (direct_adj && p.adj_kind == kAdjCompensated)
+                   ? take((size_t)p.nsx * kAdjCols * np * sizeof(float))
                    : 0;
   p.off_partial = direct_adj ? take((size_t)p.regions * np * sizeof(float4)) : 0;
   p.off_gpad = (direct_adj && p.need_gpad)
@@ -216,6 +220,7 @@ Workspace carve(const Plan& p, void* base) {
                : nullptr;
   const bool direct_adj = p.op == CGH_OP_BACKWARD && !is_separable(p.variant);
   w.rtab = (direct_adj && p.adj_kind == kAdjCompensated) ? (float2*)(b + p.off_rtab) : nullptr;
+  w.ctab = (direct_adj && p.adj_kind == kAdjCompensated) ? (float*)(b + p.off_ctab) : nullptr;
   w.partial = direct_adj ? (float*)(b + p.off_partial) : nullptr;
   w.gpad = (direct_adj && p.need_gpad) ? (float*)(b + p.off_gpad) : nullptr;
   const bool sep = is_separable(p.variant) && p.op != CGH_OP_FORWARD_F64;

@@ -100,10 +100,12 @@ constexpr int kAdjCols = 32;
 // Phase arithmetic of the adjoint kernel (Plan::adj_kind): the plain FP32
 // phase, the compensated axis phases, or the recurrence of Eq. (2) along the
 // strip row.  The compensated kind reads each row's y-phase and dy from a
-// table [ny][npad] built by a precompute launch (the same values it would
-// form itself, once per row and point instead of once per strip, row and
-// point); when that table would exceed kAdjRowTabMaxBytes the kernel forms
-// them inline instead (kAdjCompensatedInline, bitwise the same result).
+// table [ny][npad] and each strip column's x-phase from a table
+// [nsx * kAdjCols][npad], both built by one precompute launch (the same
+// values it would form itself, once per row or column and point instead of
+// once per strip and point); when either table would exceed
+// kAdjRowTabMaxBytes the kernel forms them inline instead
+// (kAdjCompensatedInline, bitwise the same result).
 constexpr int kAdjPlain = 0;
 constexpr int kAdjCompensated = 1;
 constexpr int kAdjRecurrence = 2;
@@ -153,6 +155,7 @@ struct Workspace {
   float* ytab;     // forward, compensated: [groups][npad][kCompRows]
   float* xtab;     // forward, compensated (optional): [fwd_gx * 64][npad] x-phases
   float2* rtab;    // adjoint, compensated: [ny][npad] {y-phase, y_h - y_j}
+  float* ctab;     // adjoint, compensated: [nsx * kAdjCols][npad] x-phases
   float* partial;  // adjoint: [regions][npad][4]
   float* gpad;     // adjoint: G copied to a [ny][nsx*kAdjCols] zero-padded grid
   // separable variant (tables of k2 = 2 * npad floats per row / column)
@@ -189,7 +192,7 @@ struct Plan {
   size_t off_sep_x, off_sep_y, off_sep_c, off_sep_g, off_fold_x, off_fold_y;
   size_t off_hx, off_hy, off_hg, off_hgt, off_hmax;  // half variants (hi plane; lo follows)
   size_t off_plain, off_amp, off_xrec, off_yrec, off_rec64, off_ytab, off_xtab, off_rtab,
-      off_partial, off_gpad, total;
+      off_ctab, off_partial, off_gpad, total;
 };
 
 Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op);
@@ -209,8 +212,9 @@ hipError_t launch_fill_zero_f64(double* p, int64_t count, hipStream_t s);
 hipError_t launch_prep_ytab(const float* x, const float* y, const float* z, const float* a,
                             double pitch, double wavelength, const Plan& p, const Workspace& w,
                             hipStream_t s);
-// The compensated adjoint's row table: for every row y_h and point j, the
-// compensated y-phase of y_h and y_h - y_j, from the FP32 inputs.
+// The compensated adjoint's tables, from the FP32 inputs in one launch: for
+// every row y_h and point j the compensated y-phase of y_h and y_h - y_j, and
+// for every strip column x_h and point j the compensated x-phase of x_h.
 hipError_t launch_prep_rtab(const float* x, const float* y, const float* z, const float* a,
                             double pitch, double wavelength, const Plan& p, const Workspace& w,
                             hipStream_t s);

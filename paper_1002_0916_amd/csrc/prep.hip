@@ -89,25 +89,36 @@ __global__ __launch_bounds__(256) void prep_ytab_kernel(
   }
 }
 
-// The compensated adjoint's row table: thread (g, j) forms point j's records
-// and writes, for the kRtabRows rows y_h of row group g,
-//   rtab[y_h][j] = {axis_phase(y_h) of point j, y_h - y_j},
-// the two values the adjoint kernel would otherwise form per strip.
+// The compensated adjoint's tables: thread (g, j) forms point j's records
+// and, for g < groups, writes for the kRtabRows rows y_h of row group g
+//   rtab[y_h][j] = {axis_phase(y_h) of point j, y_h - y_j};
+// the threads after those write, for the kRtabRows columns x_h of column
+// group g - groups (columns up to the last strip's end),
+//   ctab[x_h][j] = axis_phase(x_h) of point j:
+// the values the adjoint kernel would otherwise form per strip.
 constexpr int kRtabRows = 8;
 __global__ __launch_bounds__(256) void prep_rtab_kernel(
     const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
-    const float* __restrict__ a, int64_t n, int64_t npad, int ny, int64_t groups, double pitch,
-    double wavelength, float2* __restrict__ rtab) {
+    const float* __restrict__ a, int64_t n, int64_t npad, int ny, int64_t groups,
+    int64_t cgroups, double pitch, double wavelength, float2* __restrict__ rtab,
+    float* __restrict__ ctab) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= groups * npad) return;
+  if (t >= (groups + cgroups) * npad) return;
   const int64_t g = t / npad, j = t - g * npad;
   const PointRecord r = point_record(x, y, z, a, j, n, pitch, wavelength);
-  const int row0 = (int)(g * kRtabRows);
-  const int rows = min(kRtabRows, ny - row0);
-  for (int i = 0; i < rows; ++i) {
-    const float yh = (float)(row0 + i);
-    rtab[(int64_t)(row0 + i) * npad + j] =
-        make_float2(axis_phase(yh, r.yc, r.ph, r.pl, r.yb, r.yd), yh - r.y);
+  if (g < groups) {
+    const int row0 = (int)(g * kRtabRows);
+    const int rows = min(kRtabRows, ny - row0);
+    for (int i = 0; i < rows; ++i) {
+      const float yh = (float)(row0 + i);
+      rtab[(int64_t)(row0 + i) * npad + j] =
+          make_float2(axis_phase(yh, r.yc, r.ph, r.pl, r.yb, r.yd), yh - r.y);
+    }
+  } else {
+    const int64_t c0 = (g - groups) * kRtabRows;
+#pragma unroll
+    for (int k = 0; k < kRtabRows; ++k)
+      ctab[(c0 + k) * npad + j] = axis_phase((float)(c0 + k), r.xc, r.ph, r.pl, r.xb, r.xd);
   }
 }
 
@@ -149,11 +160,13 @@ hipError_t launch_prep_ytab(const float* x, const float* y, const float* z, cons
 hipError_t launch_prep_rtab(const float* x, const float* y, const float* z, const float* a,
                             double pitch, double wavelength, const Plan& p, const Workspace& w,
                             hipStream_t s) {
+  static_assert(kAdjCols % kRtabRows == 0, "column groups tile the adjoint's strips");
   const int64_t groups = (p.ny + kRtabRows - 1) / kRtabRows;
-  const unsigned blocks = grid_blocks(groups * p.npad, 256);
-  if (!blocks || !w.rtab) return hipErrorInvalidValue;
+  const int64_t cgroups = (int64_t)p.nsx * kAdjCols / kRtabRows;
+  const unsigned blocks = grid_blocks((groups + cgroups) * p.npad, 256);
+  if (!blocks || !w.rtab || !w.ctab) return hipErrorInvalidValue;
   hipLaunchKernelGGL(prep_rtab_kernel, dim3(blocks), dim3(256), 0, s, x, y, z, a, p.n, p.npad,
-                     p.ny, groups, pitch, wavelength, w.rtab);
+                     p.ny, groups, cgroups, pitch, wavelength, w.rtab, w.ctab);
   return hipGetLastError();
 }
 

@@ -113,16 +113,25 @@ def test_workspace_bytes(lib):
     rows_fit = 68 * 8 * 16384 * 4 * 4
     assert (f(*fit, B.COMPENSATED, B.OP_FORWARD) - f(*fit, B.PLAIN, B.OP_FORWARD)
             == rows_fit + 3840 * 16384 * 4)
-    # the compensated adjoint's row table, {y-phase, dy} per row and point,
-    # is N * Ny float2 while that fits in 512 MiB; above it the kernel forms
-    # the values itself and the workspace equals the plain adjoint's
+    # the compensated adjoint's tables: the row table, {y-phase, dy} per row
+    # and point (N * Ny float2), and the column table, the x-phase per strip
+    # column and point (N * ceil(Nx / 32) * 32 floats), while each fits in
+    # 512 MiB; above that the kernel forms the values itself and the
+    # workspace equals the plain adjoint's
     bp = f(1024, 1920, 1024, B.PLAIN, B.OP_BACKWARD)
-    assert b - bp == 1024 * 1024 * 8
+    assert b - bp == 1024 * 1024 * 8 + 1920 * 1024 * 4
     big = (16448, 32, 4096)
     assert big[0] * big[2] * 8 > 512 << 20
     assert f(*big, B.COMPENSATED, B.OP_BACKWARD) == f(*big, B.PLAIN, B.OP_BACKWARD)
-    edge = (4096, 32, 16384)  # exactly 512 MiB: still a table
-    assert f(*edge, B.COMPENSATED, B.OP_BACKWARD) - f(*edge, B.PLAIN, B.OP_BACKWARD) == 512 << 20
+    edge = (4096, 32, 16384)  # a row table of exactly 512 MiB: still the tables
+    assert (f(*edge, B.COMPENSATED, B.OP_BACKWARD) - f(*edge, B.PLAIN, B.OP_BACKWARD)
+            == (512 << 20) + 32 * 4096 * 4)
+    wide = (16448, 8192, 4)  # a column table above 512 MiB: none
+    assert wide[0] * wide[1] * 4 > 512 << 20
+    assert f(*wide, B.COMPENSATED, B.OP_BACKWARD) == f(*wide, B.PLAIN, B.OP_BACKWARD)
+    wide_edge = (4096, 32768, 4)  # a column table of exactly 512 MiB: the tables
+    assert (f(*wide_edge, B.COMPENSATED, B.OP_BACKWARD) - f(*wide_edge, B.PLAIN, B.OP_BACKWARD)
+            == 4 * 4096 * 8 + (512 << 20))
     for v in (p, c, d, b):
         assert v % 256 == 0
     # monotone in N
