@@ -177,6 +177,20 @@ def test_f64_kernel_mesh_sampled(oracle_mod):
     assert err <= 1e-11
 
 
+def test_f64_kernel_mesh64k_sampled(oracle_mod):
+    """The FP64 GPU forward on the 65,536-point mesh cloud (the error
+    reference of the FP32 variants at that workload)."""
+    dev = device()
+    c = W.mesh_clouds()[1]
+    x, y, z, a = to_dev(c, dev)
+    I = B.forward_f64(x, y, z, a, 1920, 1080).cpu().numpy()
+    px, py = W.sample_pixels(35, 1920, 1080, 512)
+    ref = oracle_mod.forward_at(*c.astuple(), 1920, 1080, px, py, threads=0)
+    err = max_err_frac(I[py, px], ref, c)
+    say("f64 mesh64k max|dI|/sum|A| =", err)
+    assert err <= 1e-11
+
+
 @pytest.mark.parametrize("variant", ["plain", "compensated"])
 def test_eightfold_symmetry_bitwise(variant):
     """(The separable variant multiplies A into the row table, so swapping x
