@@ -93,6 +93,7 @@ extern "C" {
 #define CGH_EINVAL 1
 #define CGH_EWORKSPACE 2
 #define CGH_EHIP 3
+#define CGH_ETOOBIG 4
 
 /* Phase-arithmetic variants. */
 #define CGH_PLAIN 0
@@ -167,11 +168,37 @@ int cgh_backward(const float* x, const float* y, const float* z, const float* a,
                  const float* grad_hologram, float* grad_x, float* grad_y, float* grad_z,
                  float* grad_a, void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * Forward as cgh_forward, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  It takes no workspace and calls no allocator: its scratch is a
+ * static device buffer of CGH_NOALLOC_SCRATCH_BYTES (64 MiB) on each GPU the
+ * library is loaded on, held until the process ends.  The caller still
+ * passes the inputs and the output (`hologram`, device float32[ny][nx]).
+ * Same kernels, same results (bitwise) as cgh_forward for every variant.
+ *   Returns CGH_ETOOBIG (before anything is enqueued) when the problem needs
+ * more scratch than the buffer holds: about 84 bytes per point plus the
+ * variant's tables (the compensated forward: 4 bytes per point and row, and
+ * 4 per point and column unless dropped to fit, since the kernel can form
+ * those values itself; the separable forms: their GEMM tables and split-K
+ * planes).  At 1920 x 1024 with 1,024 points every variant fits.
+ *   Every call on a GPU shares that GPU's buffer, which keeps the last call's
+ * contents (each call rewrites what it reads): calls that overlap on one GPU
+ * (on different streams, or from several threads without ordering) race.
+ * Order them on one stream.  The first call on each device looks up the
+ * buffer's device address (not a stream operation).  Other errors as
+ * cgh_forward.
+ */
+#define CGH_NOALLOC_SCRATCH_BYTES 67108864
+int cgh_forward_noalloc(const float* x, const float* y, const float* z, const float* a,
+                        int64_t n, int32_t nx, int32_t ny, double pitch, double wavelength,
+                        int32_t variant, float* hologram, void* stream);
+
 /* Human-readable text for a status code (static storage, never NULL). */
 const char* cgh_strerror(int status);
 
 /* Library ABI version (major * 100 + minor): 101 adds the half-precision
- * separable variants, 102 CGH_RECURRENCE. */
+ * separable variants, 102 CGH_RECURRENCE, 103 cgh_forward_noalloc. */
 int cgh_version(void);
 
 /*

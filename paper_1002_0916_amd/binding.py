@@ -11,6 +11,8 @@ Functions mirror the C entry points:
     forward_f64(x, y, z, a, nx, ny, pitch, wavelength)        -> I  [ny, nx] fp64
     backward(x, y, z, a, grad, nx, ny, pitch, wavelength, variant)
                                                    -> (gx, gy, gz, ga) fp32 [n]
+    forward_noalloc(x, y, z, a, nx, ny, pitch, wavelength, variant, out)
+                         (cgh_forward_noalloc: no workspace, static scratch)
 
 and ``CGHFunction`` wraps forward/backward as a ``torch.autograd.Function``
 differentiable in x, y, z (metres) and a.
@@ -26,7 +28,8 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcgh.so")
 
-CGH_OK, CGH_EINVAL, CGH_EWORKSPACE, CGH_EHIP = 0, 1, 2, 3
+CGH_OK, CGH_EINVAL, CGH_EWORKSPACE, CGH_EHIP, CGH_ETOOBIG = 0, 1, 2, 3, 4
+NOALLOC_SCRATCH_BYTES = 64 << 20
 PLAIN, COMPENSATED, SEPARABLE = 0, 1, 2
 SEPARABLE_F16X3, SEPARABLE_F16, SEPARABLE_BF16 = 3, 4, 5
 RECURRENCE = 6
@@ -45,7 +48,7 @@ VARIANTS = {"plain": PLAIN, "fast": PLAIN, "compensated": COMPENSATED, "comp": C
 
 EXPORTED = ("cgh_workspace_bytes", "cgh_forward", "cgh_forward_f64", "cgh_backward",
             "cgh_strerror", "cgh_version", "cgh_profile_enable", "cgh_profile_read",
-            "cgh_profile_read_each")
+            "cgh_profile_read_each", "cgh_forward_noalloc")
 
 _lib = None
 _lock = threading.Lock()
@@ -73,6 +76,9 @@ def load_library():
         lib.cgh_forward.argtypes = [vp, vp, vp, vp, i64, i32, i32, f64, f64, i32, vp, vp,
                                     ctypes.c_size_t, vp]
         lib.cgh_forward.restype = ctypes.c_int
+        lib.cgh_forward_noalloc.argtypes = [vp, vp, vp, vp, i64, i32, i32, f64, f64, i32, vp,
+                                            vp]
+        lib.cgh_forward_noalloc.restype = ctypes.c_int
         lib.cgh_forward_f64.argtypes = [vp, vp, vp, vp, i64, i32, i32, f64, f64, vp, vp,
                                         ctypes.c_size_t, vp]
         lib.cgh_forward_f64.restype = ctypes.c_int
@@ -177,6 +183,29 @@ def forward(x, y, z, a, nx: int, ny: int, pitch: float = 8e-6, wavelength: float
     _check(lib.cgh_forward(x.data_ptr(), y.data_ptr(), z.data_ptr(), a.data_ptr(), n, nx, ny,
                            float(pitch), float(wavelength), v, out.data_ptr(), ws, wsb,
                            stream.cuda_stream))
+    return out
+
+
+def forward_noalloc(x, y, z, a, nx: int, ny: int, pitch: float = 8e-6,
+                    wavelength: float = 633e-9, variant="compensated",
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    """As ``forward`` through ``cgh_forward_noalloc``: the library takes no
+    workspace (its scratch is a static device buffer of
+    NOALLOC_SCRATCH_BYTES per GPU).  Pass ``out`` to allocate nothing at all
+    (e.g. under graph capture).  Calls that overlap on one GPU race."""
+    lib = load_library()
+    n, dev = _points(x, y, z, a)
+    nx, ny = _sizes(nx, ny)
+    v = variant_id(variant)
+    if out is None:
+        out = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+    elif (out.dtype != torch.float32 or out.device != dev or not out.is_contiguous()
+          or out.numel() != nx * ny):
+        raise ValueError("out must be a contiguous float32 tensor of ny*nx on x's device")
+    stream = torch.cuda.current_stream(dev)
+    _check(lib.cgh_forward_noalloc(x.data_ptr(), y.data_ptr(), z.data_ptr(), a.data_ptr(), n,
+                                   nx, ny, float(pitch), float(wavelength), v, out.data_ptr(),
+                                   stream.cuda_stream))
     return out
 
 

@@ -3,6 +3,8 @@
 // HIP-event timing of the main kernels.
 #include <math.h>
 
+#include <atomic>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -100,7 +102,8 @@ inline bool is_separable(int32_t v) { return v == CGH_SEPARABLE || half_mode(v) 
 
 }  // namespace
 
-Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
+Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op,
+               bool col_table) {
   Plan p{};
   p.n = n;
   p.nx = nx;
@@ -112,7 +115,8 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op) {
   p.fwd_gy = (int32_t)ceil_div(ny, kFwdRowsPerWG);
   p.comp_gy = (int32_t)ceil_div(ny, kCompRowsPerWG);
   p.groups = p.comp_gy * kCompWaves;
-  p.comp_xtab = (int64_t)p.fwd_gx * kWave * p.npad <= kCompColTabMaxBytes / (int64_t)sizeof(float);
+  p.comp_xtab = col_table && (int64_t)p.fwd_gx * kWave * p.npad <=
+                                 kCompColTabMaxBytes / (int64_t)sizeof(float);
   rec_shape(nx, ny, p.rec_k, p.rec_r);
   p.rec_gx = (int32_t)ceil_div(nx, (int64_t)kWave * p.rec_k);
   p.rec_gy = (int32_t)ceil_div(ny, (int64_t)kRecWaves * p.rec_r);
@@ -261,7 +265,7 @@ struct EventPair {
 
 struct Profiler {
   std::mutex mu;
-  bool on = false;
+  std::atomic<bool> on{false};
   std::vector<EventPair> pool;                      // idle, reusable
   std::vector<EventPair> pending[CGH_KERNEL_COUNT];  // recorded, unread
 };
@@ -275,10 +279,11 @@ constexpr size_t kMaxPending = 4096;
 
 // Records the start event of a timed launch; returns the pair to close, or a
 // pair of nulls when timing is off (or not possible).
-EventPair profile_begin(int kernel, hipStream_t s) {
+EventPair profile_begin(int kernel, hipStream_t s, bool timed = true) {
   Profiler& P = profiler();
-  std::lock_guard<std::mutex> lk(P.mu);
   EventPair e{nullptr, nullptr};
+  if (!timed || !P.on.load(std::memory_order_relaxed)) return e;  // no lock, no event
+  std::lock_guard<std::mutex> lk(P.mu);
   if (!P.on || P.pending[kernel].size() >= kMaxPending) return e;
   if (!P.pool.empty()) {
     e = P.pool.back();
@@ -335,11 +340,12 @@ inline int hip_status(hipError_t e) { return e == hipSuccess ? CGH_OK : CGH_EHIP
 // ------------------------------------------------------------- separable --
 
 // I = P Q^T with P = (A cY, -A sY) [nyp][k2], Q = (cX, sX) [nxp][k2].
-int forward_separable(const Plan& p, const Workspace& w, float* hologram, hipStream_t s) {
+int forward_separable(const Plan& p, const Workspace& w, float* hologram, hipStream_t s,
+                      bool timed) {
   hipError_t e =
       launch_sep_tables(w.xrec, w.yrec, w.amp, p.npad, p.nx, p.nxp, p.ny, p.nyp, w.sep_x, w.sep_y, s);
   if (e != hipSuccess) return CGH_EHIP;
-  const EventPair ev = profile_begin(CGH_KERNEL_FWD_SEPARABLE, s);
+  const EventPair ev = profile_begin(CGH_KERNEL_FWD_SEPARABLE, s, timed);
   if (p.sep_splits == 1) {
     e = launch_gemm_f32(true, true, w.sep_y, p.k2, w.sep_x, p.k2, hologram, p.nx, 0, p.nyp,
                         p.nxp, (int)p.k2, 1, p.ny, p.nx, nullptr, s);
@@ -384,12 +390,13 @@ int backward_separable(const Plan& p, const Workspace& w, const float* z, const 
 
 // Half-precision separable variants: the same contractions on 16-bit planes
 // (A_j, resp. G, divided by a power of two recorded in w.hmax).
-int forward_separable_half(const Plan& p, const Workspace& w, float* hologram, hipStream_t s) {
+int forward_separable_half(const Plan& p, const Workspace& w, float* hologram, hipStream_t s,
+                           bool timed) {
   const int hm = half_mode(p.variant);
   hipError_t e = launch_absmax(w.amp, p.npad, w.hmax, s);  // w.hmax cleared by prep
   if (e == hipSuccess) e = launch_sep_tables_half(hm, p, w, s);
   if (e != hipSuccess) return CGH_EHIP;
-  const EventPair ev = profile_begin(CGH_KERNEL_FWD_SEPARABLE, s);
+  const EventPair ev = profile_begin(CGH_KERNEL_FWD_SEPARABLE, s, timed);
   if (p.sep_splits == 1) {
     e = launch_gemm_half(hm, w.hy_hi, w.hy_lo, p.k2, w.hx_hi, w.hx_lo, p.k2, hologram, p.nx, 0,
                          p.nyp, p.nxp, (int)p.k2, 1, p.ny, p.nx, w.hmax, nullptr, s);
@@ -431,6 +438,49 @@ int backward_separable_half(const Plan& p, const Workspace& w, const float* z, c
   return hip_status(e);
 }
 
+// ------------------------------------------------------ static scratch --
+//
+// Scratch of cgh_forward_noalloc: a file-scope device array, one copy per GPU
+// the library is loaded on, held until the process ends.  In host code its
+// name is a host-side stand-in, not a device address, so it is never passed
+// to a kernel or a copy: the entry point takes the array's address on the
+// current device from hipGetSymbolAddress, once per device (the first call
+// there), and uses that.  Every call on a GPU shares that GPU's array.
+constexpr size_t kScratchBytes = CGH_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex scratch_mu;
+std::map<int, void*> scratch_ptr;  // device -> the array's address there
+
+int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CGH_EHIP;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  auto it = scratch_ptr.find(dev);
+  if (it != scratch_ptr.end()) {
+    *out = it->second;
+    return CGH_OK;
+  }
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return CGH_EHIP;
+  if (((uintptr_t)ptr & 255u) != 0) return CGH_EHIP;
+  scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return CGH_OK;
+}
+
+}  // namespace
+
+// Enqueues the forward for plan p with its scratch at `workspace` (the
+// caller's workspace, or the static scratch), after the argument checks.
+// timed = false skips the event timing (which creates events), for the
+// allocation-free entry point.
+int forward_run(const Plan& p, void* workspace, const float* x, const float* y, const float* z,
+                const float* a, double pitch, double wavelength, float* hologram,
+                hipStream_t s, bool timed = true);
+
 }  // namespace cgh
 
 using namespace cgh;
@@ -457,29 +507,66 @@ int cgh_forward(const float* x, const float* y, const float* z, const float* a, 
   const Plan p = make_plan(n, nx, ny, variant, CGH_OP_FORWARD);
   rc = check_workspace(p, workspace, workspace_bytes);
   if (rc) return rc;
+  return forward_run(p, workspace, x, y, z, a, pitch, wavelength, hologram, s, true);
+}
+
+int cgh_forward_noalloc(const float* x, const float* y, const float* z, const float* a,
+                        int64_t n, int32_t nx, int32_t ny, double pitch, double wavelength,
+                        int32_t variant, float* hologram, void* stream) {
+  int rc = check_common(x, y, z, a, n, nx, ny, pitch, wavelength);
+  if (rc) return rc;
+  if (!valid_variant(variant)) return CGH_EINVAL;
+  if (!hologram) return CGH_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (n == 0) return hip_status(launch_fill_zero_f32(hologram, (int64_t)nx * ny, s));
+  Plan p = make_plan(n, nx, ny, variant, CGH_OP_FORWARD);
+  // Without its column table the compensated forward needs less scratch and
+  // gives the same bits.
+  if (p.total > kScratchBytes && p.comp_xtab)
+    p = make_plan(n, nx, ny, variant, CGH_OP_FORWARD, false);
+  if (p.total > kScratchBytes) return CGH_ETOOBIG;
+  void* ws = nullptr;
+  rc = scratch_address(&ws);
+  if (rc) return rc;
+  return forward_run(p, ws, x, y, z, a, pitch, wavelength, hologram, s, false);
+}
+
+}  // extern "C"
+
+namespace cgh {
+
+int forward_run(const Plan& p, void* workspace, const float* x, const float* y, const float* z,
+                const float* a, double pitch, double wavelength, float* hologram,
+                hipStream_t s, bool timed) {
+  const int32_t variant = p.variant;
+  const int64_t n = p.n;
   const Workspace w = carve(p, workspace);
   // The compensated forward forms the records with its row-phase table.
   hipError_t e = variant == CGH_COMPENSATED
                      ? launch_prep_ytab(x, y, z, a, pitch, wavelength, p, w, s)
                      : launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, false, s);
   if (e != hipSuccess) return CGH_EHIP;
-  if (variant == CGH_SEPARABLE) return forward_separable(p, w, hologram, s);
-  if (half_mode(variant) >= 0) return forward_separable_half(p, w, hologram, s);
+  if (variant == CGH_SEPARABLE) return forward_separable(p, w, hologram, s, timed);
+  if (half_mode(variant) >= 0) return forward_separable_half(p, w, hologram, s, timed);
   if (variant == CGH_COMPENSATED) {
-    const EventPair ev = profile_begin(CGH_KERNEL_FWD_COMPENSATED, s);
+    const EventPair ev = profile_begin(CGH_KERNEL_FWD_COMPENSATED, s, timed);
     e = launch_fwd_comp(p, w, hologram, s);
     profile_end(CGH_KERNEL_FWD_COMPENSATED, ev, s);
   } else if (variant == CGH_RECURRENCE) {
-    const EventPair ev = profile_begin(CGH_KERNEL_FWD_RECURRENCE, s);
+    const EventPair ev = profile_begin(CGH_KERNEL_FWD_RECURRENCE, s, timed);
     e = launch_fwd_rec(p, w, hologram, s);
     profile_end(CGH_KERNEL_FWD_RECURRENCE, ev, s);
   } else {
-    const EventPair ev = profile_begin(CGH_KERNEL_FWD_PLAIN, s);
+    const EventPair ev = profile_begin(CGH_KERNEL_FWD_PLAIN, s, timed);
     e = launch_fwd_plain(p, w, hologram, s);
     profile_end(CGH_KERNEL_FWD_PLAIN, ev, s);
   }
   return hip_status(e);
 }
+
+}  // namespace cgh
+
+extern "C" {
 
 int cgh_forward_f64(const float* x, const float* y, const float* z, const float* a, int64_t n,
                     int32_t nx, int32_t ny, double pitch, double wavelength, double* hologram,
@@ -563,12 +650,15 @@ const char* cgh_strerror(int status) {
       return "workspace missing, misaligned or too small";
     case CGH_EHIP:
       return "HIP launch or runtime error";
+    case CGH_ETOOBIG:
+      return "problem needs more scratch than the allocation-free entry point's static buffer "
+             "holds";
     default:
       return "unknown status";
   }
 }
 
-int cgh_version(void) { return 102; }
+int cgh_version(void) { return 103; }
 
 int cgh_profile_enable(int32_t on) {
   Profiler& P = profiler();

@@ -195,7 +195,10 @@ struct Plan {
       off_ctab, off_partial, off_gpad, total;
 };
 
-Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op);
+// col_table = false plans the compensated forward without its column table
+// (the kernel then forms the x-phases itself: the same bits, less scratch).
+Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op,
+               bool col_table = true);
 Workspace carve(const Plan& p, void* base);
 
 // Launch wrappers (return the hipError_t of the launch).

@@ -69,7 +69,7 @@ def test_binding_constants_match_header():
 
 
 def test_strerror_and_version(lib):
-    for code in range(4):
+    for code in range(5):
         assert isinstance(lib.cgh_strerror(code), bytes) and lib.cgh_strerror(code)
     assert lib.cgh_strerror(99) == b"unknown status"
     assert lib.cgh_version() >= 100
@@ -174,6 +174,31 @@ def test_forward_rejects_bad_arguments(lib, case):
                          args["ny"], args["pitch"], args["wl"], args["v"], args["out"], p,
                          1 << 30, None)
     assert rc == B.CGH_EINVAL
+    # the allocation-free forward runs the same checks first
+    rc = lib.cgh_forward_noalloc(args["x"], args["y"], args["z"], args["a"], args["n"],
+                                 args["nx"], args["ny"], args["pitch"], args["wl"], args["v"],
+                                 args["out"], None)
+    assert rc == B.CGH_EINVAL
+
+
+def test_noalloc_rejects_problems_beyond_its_scratch(lib):
+    """cgh_forward_noalloc refuses, on the host, any problem whose plan needs
+    more than its static buffer; the compensated forward first drops its
+    column table (the kernel forms those values itself)."""
+    from paper_1002_0916_amd import binding as B
+
+    p = ctypes.c_void_p(256)
+    cap = B.NOALLOC_SCRATCH_BYTES
+    assert lib.cgh_workspace_bytes(16384, 3840, 2160, B.PLAIN, B.OP_FORWARD) < cap
+    # the compensated forward at 3840 x 2160, N = 16384: 142 MB of row table
+    assert lib.cgh_workspace_bytes(16384, 3840, 2160, B.COMPENSATED, B.OP_FORWARD) > cap
+    for v in (B.COMPENSATED, B.SEPARABLE, B.SEPARABLE_F16X3):
+        rc = lib.cgh_forward_noalloc(p, p, p, p, 16384, 3840, 2160, 8e-6, 633e-9, v, p, None)
+        assert rc == B.CGH_ETOOBIG, v
+    # every variant fits at the paper's shape
+    for v in set(B.VARIANTS.values()):
+        assert lib.cgh_workspace_bytes(1024, 1920, 1024, v, B.OP_FORWARD) <= cap, v
+    assert b"static buffer" in lib.cgh_strerror(B.CGH_ETOOBIG)
 
 
 def test_workspace_too_small_or_misaligned(lib):
