@@ -42,35 +42,31 @@ constexpr int kRows = 8;
 constexpr int kFwdThreads = kFwdWaves * kWave;
 constexpr int kFwdRowsPerWG = kFwdWaves * kRows;
 // Points are processed in unrolled groups of kUnroll; the compensated
-// forward stages the x-phases of kTile points at a time in LDS (row stride
-// kTilePitch floats, padded so that lane-per-point writes hit distinct banks).  The point
-// arrays in the workspace are padded to a multiple of kPointPad with
-// zero-amplitude points.
+// forward stages kTile points at a time in LDS.  The point arrays in the
+// workspace are padded to a multiple of kPointPad with zero-amplitude
+// points.
 constexpr int kUnroll = 4;
 constexpr int kTile = 64;
 constexpr int kTilePitch = kWave + 1;
 
 // Compensated forward: a workgroup of kCompWaves waves covers 64 columns x
-// (kCompWaves * kCompRows) rows; each wave owns kCompRows rows and consumes
-// kCompUnroll points per round trip of scalar loads (kCompUnroll * kCompRows
-// row phases + amplitudes in SGPRs, double buffered).  Overridable at build
-// time for tuning experiments.
+// (kCompWaves * kCompRows) rows; each wave owns kCompRows rows.  Its x-phases,
+// row phases and amplitudes are staged in LDS a tile of kTile points at a
+// time (x-phase rows padded to kTilePitch floats, so that lane-per-point
+// writes hit distinct banks).  Overridable at build time for tuning
+// experiments.
 #ifndef CGH_COMP_WAVES
 #define CGH_COMP_WAVES 8
 #endif
 #ifndef CGH_COMP_ROWS
 #define CGH_COMP_ROWS 4
 #endif
-#ifndef CGH_COMP_UNROLL
-#define CGH_COMP_UNROLL 8
-#endif
 constexpr int kCompWaves = CGH_COMP_WAVES;
 constexpr int kCompRows = CGH_COMP_ROWS;
-constexpr int kCompUnroll = CGH_COMP_UNROLL;
 constexpr int kCompThreads = kCompWaves * kWave;
 constexpr int kCompRowsPerWG = kCompWaves * kCompRows;
 static_assert(kWave % kCompWaves == 0, "x-phase fill splits the 64 columns over the waves");
-static_assert(kTile % (2 * kCompUnroll) == 0, "tiles hold whole ping-pong group pairs");
+static_assert(kTile % 16 == 0, "the inner loop takes 16 points per iteration");
 // The compensated forward reads its x-phases from a column table
 // [fwd_gx * 64][npad] while that takes at most kCompColTabMaxBytes, else it
 // forms them per workgroup (the same values).  Every row block of

@@ -181,138 +181,107 @@ __global__ __launch_bounds__(kRecThreads * S) void fwd_rec_kernel(const float4* 
 // Compensated FP32: the phase separates exactly as X_j(x_h) + Y_j(y_h) with
 // X_j(x_h) = Prev (x_h - x_j)^2 and Y_j(y_h) = Prev (y_h - y_j)^2.  Each part
 // is formed on the integer pixel grid as a compensated split product reduced
-// mod 1 (axis_phase).  Y comes from the per-row table (wave-uniform, scalar
-// loads).  X depends on the column and the point only, and the kCompWaves
-// waves of a workgroup share their 64 columns, so the workgroup stages X for
-// a tile of kTile points in LDS, double buffered so that filling tile t+1
-// overlaps consuming tile t.  For the fill, lane l holds point l of the tile
-// and wave w the kWave / kCompWaves columns from w kWave / kCompWaves on.
-// With TAB the values come from the column table xtab[col][npad] (built with
-// the row table; buffer loads issued a tile before their LDS store, no
-// arithmetic), else each lane forms them from its point's record (a vector
-// load issued a tile ahead).
-// Either way they are the same bits.  Per interaction: one LDS-fed add, the
-// native cosine (no fract: the sum stays within a few revolutions) and one
-// fma.
+// mod 1 (axis_phase).  Lane l of a wave owns column col0 + l and the wave
+// kCompRows rows; the kCompWaves waves of a workgroup share their 64
+// columns.  Per tile of kTile points the workgroup stages in LDS the x-phases
+// [point][column] (from the column table xtab[col][npad] with TAB, else
+// formed from each point's record: the same bits), each wave's row phases
+// [point] (one float4 of the row table: its kCompRows rows) and the
+// amplitudes.  The inner loop reads X per lane and Y and A as broadcast LDS
+// reads (every lane the same address), so every operand of the per-
+// interaction add, cosine and fma is a VGPR: on gfx950 such FP32 instructions
+// issue about 1.7 times as fast as ones reading an SGPR, and without SGPR
+// buffers the kernel fits eight waves per SIMD.  The tile is single-buffered
+// (25 KB of LDS): the next tile's values are loaded into registers while the
+// current one is consumed and stored between two barriers.  Per interaction:
+// one add, the native cosine (no fract: the sum stays within a few
+// revolutions) and one fma.
 template <bool TAB>
 __device__ __forceinline__ void fwd_comp_body(const float* __restrict__ xrec,
-                                              const float* __restrict__ xtab,
-                                              const float* __restrict__ amp,
-                                              const float* __restrict__ ytab, int npad, int nx,
-                                              int ny, float* __restrict__ out) {
-  __shared__ float xs[2][kTile * kTilePitch];
+                                                  const float* __restrict__ xtab,
+                                                  const float* __restrict__ amp,
+                                                  const float* __restrict__ ytab, int npad,
+                                                  int nx, int ny, float* __restrict__ out) {
+  static_assert(kCompRows == 4, "a wave's row phases of one point are one float4");
+  __shared__ float xs[kTile * kTilePitch];
+  __shared__ float4 ys[kCompWaves][kTile];
+  __shared__ float4 as4[kTile / 4];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  // Tiles of one tile row share their row-phase table: keep them on one XCD.
   const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int bx = (int)(tile % gridDim.x), by = (int)(tile / gridDim.x);
   const int col = bx * kWave + lane;
   const int col0 = bx * kWave;
   const int grp = by * kCompWaves + wave;
-  const float* __restrict__ yt = ytab + (int64_t)grp * npad * kCompRows;
+  const float4* __restrict__ yt = reinterpret_cast<const float4*>(ytab) + (int64_t)grp * npad;
   const int ntiles = npad / kTile;
   constexpr int kColsPerWave = kWave / kCompWaves;
-
-  // This lane's point record {c, Ph, Pl, b, d} for the tile being filled
-  // (inline form), or the tile's column values (table form: the column's
-  // byte offset is a scalar operand of a buffer load, the lane's a vector
-  // one; the descriptor spans the table, gridDim.x * 64 columns of npad).
-  auto load_rec = [&](int tile, float4& r0, float& r1) {
-    const float* r = xrec + (int64_t)(tile * kTile + lane) * kAxisRec;
-    r0 = *reinterpret_cast<const float4*>(r);
-    r1 = r[4];
-  };
   const __amdgpu_buffer_rsrc_t xtab_rsrc = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(xtab), 0, TAB ? (int)((int64_t)gridDim.x * kWave * npad * 4) : 0,
       0x00020000);
-  auto load_cols = [&](int tile, float* xv) {
+
+  // Registers holding the next tile: lane l of wave w has point l's x-phases
+  // of the wave's kColsPerWave columns (or its record), its row phases, and
+  // (wave 0) its amplitude.
+  float xv[kColsPerWave];
+  float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), yv;
+  float r1 = 0.f, av = 0.f;
+  auto load_tile = [&](int t) {
+    const int j = t * kTile + lane;
+    if (TAB) {
 #pragma unroll
-    for (int k = 0; k < kColsPerWave; ++k) {
-      const int c = col0 + wave * kColsPerWave + k;
-      xv[k] = __builtin_bit_cast(
-          float, __builtin_amdgcn_raw_buffer_load_b32(
-                     xtab_rsrc, (unsigned)lane * 4u,
-                     (int)(((int64_t)c * npad + (int64_t)tile * kTile) * 4), 0));
+      for (int k = 0; k < kColsPerWave; ++k) {
+        const int c = col0 + wave * kColsPerWave + k;
+        xv[k] = __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(
+                       xtab_rsrc, (unsigned)lane * 4u,
+                       (int)(((int64_t)c * npad + (int64_t)t * kTile) * 4), 0));
+      }
+    } else {
+      const float* r = xrec + (int64_t)j * kAxisRec;
+      r0 = *reinterpret_cast<const float4*>(r);
+      r1 = r[4];
     }
+    yv = yt[j];
+    if (wave == 0) av = amp[j];
   };
-  auto fill = [&](int buf, const float4& r0, float r1) {
+  auto store_tile = [&]() {
 #pragma unroll
     for (int k = 0; k < kColsPerWave; ++k) {
       const int c = wave * kColsPerWave + k;
-      xs[buf][lane * kTilePitch + c] = axis_phase((float)(col0 + c), r0.x, r0.y, r0.z, r0.w, r1);
+      xs[lane * kTilePitch + c] =
+          TAB ? xv[k] : axis_phase((float)(col0 + c), r0.x, r0.y, r0.z, r0.w, r1);
     }
-  };
-  auto store_cols = [&](int buf, const float* xv) {
-#pragma unroll
-    for (int k = 0; k < kColsPerWave; ++k)
-      xs[buf][lane * kTilePitch + wave * kColsPerWave + k] = xv[k];
-  };
-  // Row phases and amplitudes of kCompUnroll consecutive points, read
-  // through scalar loads (SGPRs) and software-pipelined one group ahead: the
-  // loads of the next group are issued only after the first use of the
-  // current group (which waits for all outstanding scalar and LDS traffic),
-  // so the rest of the group's arithmetic covers their latency.
-  auto load_group = [&](int j, float* yv, float* av) {
-    const float* src = yt + (int64_t)j * kCompRows;
-#pragma unroll
-    for (int k = 0; k < kCompUnroll * kCompRows; ++k) yv[k] = src[k];
-#pragma unroll
-    for (int u = 0; u < kCompUnroll; ++u) av[u] = amp[j + u];
+    ys[wave][lane] = yv;
+    if (wave == 0) reinterpret_cast<float*>(as4)[lane] = av;
   };
 
   float acc[kCompRows];
 #pragma unroll
   for (int i = 0; i < kCompRows; ++i) acc[i] = 0.0f;
-  // Two ping-pong SGPR buffers; the last group re-reads itself (in bounds).
-  auto do_group = [&](const float* xt, int t, int p, const float* yv, const float* av,
-                      float* yn, float* an) {
-    float X[kCompUnroll];
-#pragma unroll
-    for (int u = 0; u < kCompUnroll; ++u) X[u] = xt[(p + u) * kTilePitch + lane];
-#pragma unroll
-    for (int i = 0; i < kCompRows; ++i)
-      acc[i] = __builtin_fmaf(av[0], cos_rev(X[0] + yv[i]), acc[i]);
-    __builtin_amdgcn_sched_barrier(0);
-    load_group(min(t * kTile + p + kCompUnroll, npad - kCompUnroll), yn, an);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int u = 1; u < kCompUnroll; ++u) {
-#pragma unroll
-      for (int i = 0; i < kCompRows; ++i)
-        acc[i] = __builtin_fmaf(av[u], cos_rev(X[u] + yv[u * kCompRows + i]), acc[i]);
-    }
-  };
-  float yA[kCompUnroll * kCompRows], aA[kCompUnroll], yB[kCompUnroll * kCompRows], aB[kCompUnroll];
-  float4 r0;
-  float r1;
-  float xv[kColsPerWave];
-  if (TAB) {
-    load_cols(0, xv);
-    store_cols(0, xv);
-    if (ntiles > 1) load_cols(1, xv);
-  } else {
-    load_rec(0, r0, r1);
-    fill(0, r0, r1);
-    if (ntiles > 1) load_rec(1, r0, r1);
-  }
-  load_group(0, yA, aA);
-  __syncthreads();
+  load_tile(0);
   for (int t = 0; t < ntiles; ++t) {
-    if (t + 1 < ntiles) {
-      if (TAB) {
-        store_cols((t + 1) & 1, xv);
-        if (t + 2 < ntiles) load_cols(t + 2, xv);
-      } else {
-        fill((t + 1) & 1, r0, r1);
-        if (t + 2 < ntiles) load_rec(t + 2, r0, r1);
+    if (t > 0) __syncthreads();  // every wave is done with the previous tile
+    store_tile();
+    __syncthreads();
+    if (t + 1 < ntiles) load_tile(t + 1);
+#pragma unroll 2
+    for (int p = 0; p < kTile; p += 8) {
+#pragma unroll
+      for (int q = 0; q < 8; q += 4) {
+        const float4 a4 = as4[(p + q) / 4];
+        const float A[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float X = xs[(p + q + u) * kTilePitch + lane];
+          const float4 y4 = ys[wave][p + q + u];
+          acc[0] = __builtin_fmaf(A[u], cos_rev(X + y4.x), acc[0]);
+          acc[1] = __builtin_fmaf(A[u], cos_rev(X + y4.y), acc[1]);
+          acc[2] = __builtin_fmaf(A[u], cos_rev(X + y4.z), acc[2]);
+          acc[3] = __builtin_fmaf(A[u], cos_rev(X + y4.w), acc[3]);
+        }
       }
     }
-    const float* xt = xs[t & 1];
-    for (int p = 0; p < kTile; p += 2 * kCompUnroll) {
-      do_group(xt, t, p, yA, aA, yB, aB);
-      do_group(xt, t, p + kCompUnroll, yB, aB, yA, aA);
-    }
-    __syncthreads();
   }
   const int y0 = grp * kCompRows;
   if (col < nx) {
@@ -322,11 +291,9 @@ __device__ __forceinline__ void fwd_comp_body(const float* __restrict__ xrec,
   }
 }
 
-__global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(const float* __restrict__ xtab,
-                                                               const float* __restrict__ amp,
-                                                               const float* __restrict__ ytab,
-                                                               int npad, int nx, int ny,
-                                                               float* __restrict__ out) {
+__global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(
+    const float* __restrict__ xtab, const float* __restrict__ amp, const float* __restrict__ ytab,
+    int npad, int nx, int ny, float* __restrict__ out) {
   fwd_comp_body<true>(nullptr, xtab, amp, ytab, npad, nx, ny, out);
 }
 

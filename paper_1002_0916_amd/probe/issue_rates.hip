@@ -1,13 +1,17 @@
 // Machine constants behind the roofline model (a standalone gfx950 program,
-// not part of the library): the issue rate of FP32 FMA, v_cos_f32, v_sin_f32
-// and v_fract_f32, alone and mixed, in issue slots relative to an FMA, and the
-// accuracy of v_cos_f32 / v_sin_f32 (cos and sin of 2 pi t) against the host's
-// FP64 libm.
+// not part of the library): the issue cost of FP32 VALU instructions by kind
+// (all operands in VGPRs, or one read from an SGPR), of v_cos_f32,
+// v_sin_f32 and v_fract_f32, and of the per-interaction instruction mix of
+// each hot kernel, in cycles per 64-lane instruction per CU; and the
+// accuracy of v_cos_f32 / v_sin_f32 (cos and sin of 2 pi t) against the
+// host's FP64 libm.
 //
-// Rates: 4096 workgroups of 256 threads (16 waves per SIMD), each thread
-// running 8 independent dependency chains for 4096 steps, so the measurement
-// is issue-bound, not latency-bound.  A step of a mixed mode issues one
-// instruction of each listed kind per chain.  Best of 4 launches.
+// Rates: workgroups of 256 threads (4096 of them: 16 waves per SIMD, or 2048:
+// 8), each thread running 8 independent dependency chains for 4096 steps, so
+// the measurement is issue-bound, not latency-bound.  A step of a mixed mode
+// issues one instruction of each listed kind per chain.  Values that are
+// wave-uniform in the kernels (a, b) are SGPR operands; av, bv hold the same
+// values in VGPRs (0 * t is not folded under strict FP).  Best of 4 launches.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -24,43 +28,99 @@
   } while (0)
 
 constexpr int kChains = 8;
+constexpr int kModes = 16;
+const char* const kNames[kModes] = {
+    "fma (v, s, s)",  "fma (v, v, v)",   "add (v, s)",        "add (v, v)",
+    "fract",          "cos",             "sin",               "cos + sin",
+    "cos + fma(v,s,s)", "cos + 4 fma(v,s,s)",
+    "fwd compensated: add, cos, fma (A, Y in VGPRs)",
+    "fwd compensated: add, cos, fma (A, Y in SGPRs)",
+    "fwd plain: sub, fma, mul, fract, cos, fma (point in SGPRs)",
+    "adj compensated: add, sin, cos, 3 fma (G in SGPR)",
+    "adj compensated: add, sin, cos, 3 fma (G in VGPR)",
+    "adj plain: fma, mul, fract, sin, cos, 3 fma (G in SGPR)"};
 
 template <int MODE>
 __global__ void rate(float* out, int iters, float a, float b) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  float x[kChains], y[kChains];
+  const float av = __builtin_fmaf(0.0f, (float)t, a), bv = __builtin_fmaf(0.0f, (float)t, b);
+  float x[kChains], y[kChains], s0[kChains], s1[kChains], s2[kChains];
 #pragma unroll
   for (int k = 0; k < kChains; ++k) {
     x[k] = 0.001f * (t + k);
     y[k] = 0.002f * (t - k);
+    s0[k] = s1[k] = s2[k] = 0.0f;
   }
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
     for (int k = 0; k < kChains; ++k) {
-      if (MODE == 0) x[k] = __builtin_amdgcn_cosf(x[k]);
-      if (MODE == 1) x[k] = __builtin_amdgcn_sinf(x[k]);
-      if (MODE == 2) x[k] = __builtin_amdgcn_fractf(x[k] + a);
-      if (MODE == 3) x[k] = __builtin_fmaf(x[k], a, b);
-      if (MODE == 4) {
+      if (MODE == 0) x[k] = __builtin_fmaf(x[k], a, b);
+      if (MODE == 1) x[k] = __builtin_fmaf(x[k], av, bv);
+      if (MODE == 2) x[k] = x[k] + a;
+      if (MODE == 3) x[k] = x[k] + bv;
+      if (MODE == 4) x[k] = __builtin_amdgcn_fractf(x[k]);
+      if (MODE == 5) x[k] = __builtin_amdgcn_cosf(x[k]);
+      if (MODE == 6) x[k] = __builtin_amdgcn_sinf(x[k]);
+      if (MODE == 7) {
+        x[k] = __builtin_amdgcn_cosf(x[k]);
+        y[k] = __builtin_amdgcn_sinf(y[k]);
+      }
+      if (MODE == 8) {
         x[k] = __builtin_amdgcn_cosf(x[k]);
         y[k] = __builtin_fmaf(y[k], a, b);
       }
-      if (MODE == 5) {
+      if (MODE == 9) {
         x[k] = __builtin_amdgcn_cosf(x[k]);
 #pragma unroll
         for (int f = 0; f < 4; ++f) y[k] = __builtin_fmaf(y[k], a, b);
       }
-      if (MODE == 6) {
-        x[k] = __builtin_amdgcn_cosf(x[k]);
-        y[k] = __builtin_amdgcn_sinf(y[k]);
+      if (MODE == 10 || MODE == 11) {  // X + Y, cos, A * c + acc
+        const float c = __builtin_amdgcn_cosf(x[k] + (MODE == 10 ? bv : b));
+        s0[k] = __builtin_fmaf(MODE == 10 ? av : a, c, s0[k]);
+        x[k] = x[k] + (MODE == 10 ? bv : b);
+      }
+      if (MODE == 12) {  // dy, r2, Prev r2, fract, cos, acc
+        const float dy = x[k] - b;
+        const float r2 = __builtin_fmaf(dy, dy, y[k]);
+        const float c = __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(a * r2));
+        s0[k] = __builtin_fmaf(a, c, s0[k]);
+        x[k] = dy;
+      }
+      if (MODE == 13 || MODE == 14) {  // t = CX + RY, sin, cos, Sc, row sum, column sum
+        const float g = MODE == 13 ? a : av;
+        const float tt = x[k] + bv;
+        const float sn = __builtin_amdgcn_sinf(tt), cs = __builtin_amdgcn_cosf(tt);
+        s0[k] = __builtin_fmaf(g, cs, s0[k]);
+        s1[k] = __builtin_fmaf(g, sn, s1[k]);
+        s2[k] = __builtin_fmaf(g, sn, s2[k]);
+        x[k] = tt;
+      }
+      if (MODE == 15) {  // fract(Prev (dx^2 + RY)), sin, cos, 3 sums
+        const float tt = __builtin_amdgcn_fractf(bv * __builtin_fmaf(x[k], x[k], y[k]));
+        const float sn = __builtin_amdgcn_sinf(tt), cs = __builtin_amdgcn_cosf(tt);
+        s0[k] = __builtin_fmaf(a, cs, s0[k]);
+        s1[k] = __builtin_fmaf(a, sn, s1[k]);
+        s2[k] = __builtin_fmaf(a, sn, s2[k]);
+        x[k] = tt;
       }
     }
   }
   float s = 0.f;
 #pragma unroll
-  for (int k = 0; k < kChains; ++k) s += x[k] + y[k];
+  for (int k = 0; k < kChains; ++k) s += x[k] + y[k] + s0[k] + s1[k] + s2[k];
   out[t] = s;  // keeps every chain live
 }
+
+template <int M>
+void launch(int blocks, float* d, int iters) {
+  rate<M><<<blocks, 256>>>(d, iters, 1.0001f, 0.5f);
+}
+
+typedef void (*Launch)(int, float*, int);
+template <int... M>
+struct Table {
+  static constexpr Launch fns[] = {launch<M>...};
+};
 
 __global__ void trig(const float* in, float* oc, float* os, int n) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -75,43 +135,37 @@ int main() {
   CK(hipGetDeviceProperties(&p, 0));
   printf("device %s, %d CUs, clock %d kHz, %s\n", p.name, p.multiProcessorCount, p.clockRate,
          p.gcnArchName);
-  const int blocks = 4096, threads = 256, iters = 4096;
+  const int iters = 4096;
   float* d;
-  CK(hipMalloc(&d, sizeof(float) * blocks * threads));
+  CK(hipMalloc(&d, sizeof(float) * 4096 * 256));
   hipEvent_t e0, e1;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
-  const char* names[] = {"cos", "sin", "add+fract", "fma", "cos+fma", "cos+4fma", "cos+sin"};
-  double rate_of[7];
-  for (int mode = 0; mode < 7; ++mode) {
-    float best = 1e30f;
-    for (int rep = 0; rep < 4; ++rep) {
-      CK(hipEventRecord(e0));
-      switch (mode) {
-        case 0: rate<0><<<blocks, threads>>>(d, iters, 1.0001f, 0.5f); break;
-        case 1: rate<1><<<blocks, threads>>>(d, iters, 1.0001f, 0.5f); break;
-        case 2: rate<2><<<blocks, threads>>>(d, iters, 1.0001f, 0.5f); break;
-        case 3: rate<3><<<blocks, threads>>>(d, iters, 1.0001f, 0.5f); break;
-        case 4: rate<4><<<blocks, threads>>>(d, iters, 1.0001f, 0.5f); break;
-        case 5: rate<5><<<blocks, threads>>>(d, iters, 1.0001f, 0.5f); break;
-        default: rate<6><<<blocks, threads>>>(d, iters, 1.0001f, 0.5f); break;
+  const Launch* fns = Table<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15>::fns;
+  // One 64-lane instruction per CU per clock.
+  const double per_cycle = (double)p.multiProcessorCount * 64 * (p.clockRate * 1e3);
+  printf("\ncycles per step (one 64-lane instruction per CU per clock = 1)\n");
+  printf("%-60s %10s %10s\n", "step", "16 waves", "8 waves");
+  for (int mode = 0; mode < kModes; ++mode) {
+    double cyc[2];
+    for (int w = 0; w < 2; ++w) {
+      const int blocks = w == 0 ? 4096 : 2048;
+      float best = 1e30f;
+      for (int rep = 0; rep < 4; ++rep) {
+        CK(hipEventRecord(e0));
+        fns[mode](blocks, d, iters);
+        CK(hipGetLastError());
+        CK(hipEventRecord(e1));
+        CK(hipEventSynchronize(e1));
+        float ms;
+        CK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) best = ms;
       }
-      CK(hipGetLastError());
-      CK(hipEventRecord(e1));
-      CK(hipEventSynchronize(e1));
-      float ms;
-      CK(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best) best = ms;
+      const double steps = (double)blocks * 256 * iters * kChains;
+      cyc[w] = per_cycle * best * 1e-3 / steps;
     }
-    rate_of[mode] = (double)blocks * threads * iters * kChains / (best * 1e-3);
+    printf("%-60s %10.3f %10.3f\n", kNames[mode], cyc[0], cyc[1]);
   }
-  const double fma = rate_of[3];
-  const double peak = (double)p.multiProcessorCount * 64 * (p.clockRate * 1e3);
-  printf("\n%-10s %16s %22s\n", "step", "steps/s (lanes)", "issue slots (FMA = 1)");
-  for (int mode = 0; mode < 7; ++mode)
-    printf("%-10s %16.4e %22.2f\n", names[mode], rate_of[mode], fma / rate_of[mode]);
-  printf("\nFMA rate %.4e lane-ops/s = %.1f%% of %d CUs x 64 lanes x %.2f GHz\n", fma,
-         100.0 * fma / peak, p.multiProcessorCount, p.clockRate * 1e-6);
 
   // Accuracy of cos(2 pi t) and sin(2 pi t) over 2^24 points of each range.
   const int n = 1 << 24;
