@@ -36,41 +36,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Peak FP32 VALU issue rate of MI355X without packed math: 256 CUs x 4 SIMDs x
-# 16 lanes x 2.4 GHz lane-instructions per second.  Transcendentals (v_cos_f32,
-# v_sin_f32) issue at half rate on gfx950 (measured), i.e. 2 slots each.
-PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
-TRANS_SLOTS = 2
-# Algorithmic VALU issue slots per point-pixel interaction of each kernel:
-#  fwd plain        dy, r2 (fma), Prev*r2, fract, cos, acc fma        = 5 + 2
-#  fwd compensated  X+Y add, cos, acc fma                             = 2 + 2
-#  adj plain        r2 (fma), Prev*r2, fract, sin, cos, Sc fma,
-#                   G*sin folded into column and row sums (2 fma)     = 6 + 4
-#  adj compensated  X+Y add, sin, cos, Sc fma, column/row sums (2)    = 4 + 4
-#  fwd recurrence   Gamma += delta, cos, acc fma (delta += Delta is
-#                   shared by the rows of a lane; seeds are overhead) = 2 + 2
-#  adj recurrence   Gamma += delta_c, sin, cos, Sc fma, column/row
-#                   sums (2) (delta_c kept per strip column)          = 4 + 4
-SLOTS = {
-    "fwd_plain": 5 + TRANS_SLOTS,
-    "fwd_compensated": 2 + TRANS_SLOTS,
-    "fwd_recurrence": 2 + TRANS_SLOTS,
-    "adj_plain": 6 + 2 * TRANS_SLOTS,
-    "adj_compensated": 4 + 2 * TRANS_SLOTS,
-    "adj_recurrence": 4 + 2 * TRANS_SLOTS,
-}
-# The same work if every packable FP32 add/mul/fma ran as packed math (two
-# lanes per slot; fract and the transcendentals do not pack).  Packed FP32 is
-# disabled for all device code here, so this stricter bound is reported beside
-# the primary (non-packed) one, not instead of it.
-SLOTS_PACKED = {
-    "fwd_plain": 4 / 2 + 1 + TRANS_SLOTS,
-    "fwd_compensated": 2 / 2 + TRANS_SLOTS,
-    "fwd_recurrence": 2 / 2 + TRANS_SLOTS,
-    "adj_plain": 5 / 2 + 1 + 2 * TRANS_SLOTS,
-    "adj_compensated": 4 / 2 + 2 * TRANS_SLOTS,
-    "adj_recurrence": 4 / 2 + 2 * TRANS_SLOTS,
-}
+# Roofline of the direct kernels, which are bound by the vector ALU.  MI355X's
+# FP32 vector peak, 157.3 TFLOP/s, is 256 CUs x 2.4 GHz x 128 FP32 lanes per
+# clock (x 2 flops per FMA): 7.86e13 FP32 lane-operations per second.  Every
+# FP32 operation of an interaction takes one slot of that rate and every
+# transcendental (v_cos_f32, v_sin_f32: quarter rate) four.  The machine probe
+# (profiles/machine_issue_rates_gfx950.md) bears this out: a 64-lane FP32
+# instruction with VGPR operands takes 0.61 of a CU clock (0.5 at the peak),
+# one reading an SGPR about 1.05, a cosine or sine 2.2 (2 at quarter rate),
+# and the transcendentals overlap neither each other nor other FP32 work.
+PEAK_FP32_LANE_OPS = 256 * 2.4e9 * 128
+TRANS_SLOTS = 4
+# Algorithmic FP32 operations (and transcendentals) per point-pixel interaction:
+#  fwd plain        dy, r2 (fma), Prev*r2, fract, acc fma  (+ cos)
+#  fwd compensated  X+Y add, acc fma                       (+ cos)
+#  fwd recurrence   Gamma += delta, acc fma (delta += Delta is shared by the
+#                   rows of a lane; seeds are overhead)     (+ cos)
+#  adj plain        r2 (fma), Prev*r2, fract, Sc fma, G*sin folded into the
+#                   column and row sums (2 fma)             (+ sin, cos)
+#  adj compensated  X+Y add, Sc fma, column/row sums (2)    (+ sin, cos)
+#  adj recurrence   Gamma += delta_c, Sc fma, column/row sums (2) (+ sin, cos)
+FP32_OPS = {"fwd_plain": 5, "fwd_compensated": 2, "fwd_recurrence": 2,
+            "adj_plain": 6, "adj_compensated": 4, "adj_recurrence": 4}
+TRANS_OPS = {"fwd_plain": 1, "fwd_compensated": 1, "fwd_recurrence": 1,
+             "adj_plain": 2, "adj_compensated": 2, "adj_recurrence": 2}
+SLOTS = {k: FP32_OPS[k] + TRANS_SLOTS * TRANS_OPS[k] for k in FP32_OPS}
+# The practical ceiling: each kernel's per-interaction instruction mix run
+# alone by the probe (issue-bound, 16 waves per SIMD, operands where the
+# kernel holds them), in CU clocks per 64 interactions.  The recurrence
+# adjoint issues the compensated adjoint's mix (an add of two VGPRs, sine,
+# cosine, three FMAs with G from an SGPR).
+MIX_CLOCKS = {"fwd_plain": 6.097, "fwd_compensated": 3.695, "adj_plain": 9.281,
+              "adj_compensated": 7.878, "adj_recurrence": 7.878}
+CU_CLOCKS_PER_S = 256 * 2.4e9
 # The separable variant is a different algorithm, bound by the FP32 matrix
 # cores (dense MFMA FP32 peak 157.3 TFLOP/s): the forward is one GEMM of
 # 2 x (2N) flops per pixel (4 flops per interaction), the adjoint two
@@ -94,7 +92,14 @@ def peak_interactions(key):
     if variant in MFMA_FLOPS:
         f_fwd, f_adj, peak = MFMA_FLOPS[variant]
         return peak / (f_fwd if op == "fwd" else f_adj)
-    return PEAK_SLOTS / SLOTS[key]
+    return PEAK_FP32_LANE_OPS / SLOTS[key]
+
+
+def mix_interactions(key):
+    """Interactions/s of the kernel's instruction mix run alone (the probe),
+    or None where the probe has no such mix."""
+    c = MIX_CLOCKS.get(key)
+    return CU_CLOCKS_PER_S * 64 / c if c else None
 
 
 def parse():
@@ -334,6 +339,12 @@ def main():
                                  peak_interactions("fwd_" + variant),
             "adj_roofline_frac": (inter / (r["adj_kernel_ms"] * 1e-3)) /
                                  peak_interactions("adj_" + variant),
+            "fwd_frac_of_mix": ((inter / (r["fwd_kernel_ms"] * 1e-3)) /
+                                mix_interactions("fwd_" + variant)
+                                if mix_interactions("fwd_" + variant) else None),
+            "adj_frac_of_mix": ((inter / (r["adj_kernel_ms"] * 1e-3)) /
+                                mix_interactions("adj_" + variant)
+                                if mix_interactions("adj_" + variant) else None),
             "max_err_vs_fp64_over_sum_abs_a": errs[variant],
             "adj_rel_l2_vs_compensated": adj_errs[variant],
         }
@@ -375,12 +386,22 @@ def main():
                               if args.variant in ADJ_KERNEL_NAME else None),
             "traffic_sized_unit": "bytes per launch (reads: TCC_EA0_RDREQ_32B/64B/128B x "
                                   "request size; writes: copy-calibrated WRITE_SIZE)",
+            "peak_basis": (
+                "FP32 vector peak 157.3 TFLOP/s = 7.86e13 FP32 lane-op/s (256 CU x 2.4 GHz x "
+                "128 lanes); per interaction %d FP32 ops + %d transcendentals x %d slots "
+                "(quarter rate) = %d slots" % (FP32_OPS[adj_key], TRANS_OPS[adj_key],
+                                                TRANS_SLOTS, SLOTS[adj_key])
+                if adj_key in SLOTS else "matrix-core peak of the GEMM operand type"),
             "slots_per_interaction": SLOTS.get(adj_key),
-            "frac_if_packed": (achieved * 1e9 / (PEAK_SLOTS / SLOTS_PACKED[adj_key])
-                               if adj_key in SLOTS_PACKED else None),
+            "trans_slots": TRANS_SLOTS if adj_key in SLOTS else None,
+            # the same instruction mix run alone on this chip (machine probe)
+            "mix_peak": (mix_interactions(adj_key) / 1e9 if mix_interactions(adj_key)
+                         else None),
+            "frac_of_mix": (achieved * 1e9 / mix_interactions(adj_key)
+                            if mix_interactions(adj_key) else None),
             "flops_per_interaction": (MFMA_FLOPS[args.variant][1]
                                       if args.variant in MFMA_FLOPS else None),
-            "peak_slots_per_s": PEAK_SLOTS,
+            "peak_lane_ops_per_s": PEAK_FP32_LANE_OPS if adj_key in SLOTS else None,
             "kernel_ms": adj_ms,
         },
         "variants": {v: kernel_summary(v) for v in results},
@@ -640,6 +661,10 @@ def report_workload(args):
             "fwd_roofline_frac": inter / (fms * 1e-3) / peak_interactions("fwd_" + variant),
             "adj_kernel_ms": ams, "adj_gpps": inter / (ams * 1e-3) / 1e9,
             "adj_roofline_frac": inter / (ams * 1e-3) / peak_interactions("adj_" + variant),
+            "fwd_frac_of_mix": (inter / (fms * 1e-3) / mix_interactions("fwd_" + variant)
+                                if mix_interactions("fwd_" + variant) else None),
+            "adj_frac_of_mix": (inter / (ams * 1e-3) / mix_interactions("adj_" + variant)
+                                if mix_interactions("adj_" + variant) else None),
             "max_err_vs_fp64_over_sum_abs_a": err,
         }
     if args.workload == "fit4k":
@@ -1066,11 +1091,154 @@ def summarize_counters(root):
     _write_md("counters_paper_1920x1024_n1024.md", lines)
 
 
+def _json_lines(root, mode):
+    """The JSON report lines of `mode` in the *.log files under root."""
+    found = []
+    for f in _csv_files(root, "*.log"):
+        with open(f) as fh:
+            for text in fh:
+                if text.startswith("{"):
+                    d = json.loads(text)
+                    if d.get("mode") == mode:
+                        found.append(d)
+    if not found:
+        raise SystemExit("no %s report line under %s" % (mode, root))
+    return found
+
+
+def _linear_fit(xs, ys):
+    """Least-squares t = a + b N: (a, b, R^2, largest |residual| / t)."""
+    n = len(xs)
+    mx, my = sum(xs) / n, sum(ys) / n
+    sxx = sum((x - mx) ** 2 for x in xs)
+    b = sum((x - mx) * (y - my) for x, y in zip(xs, ys)) / sxx
+    a = my - b * mx
+    res = [y - (a + b * x) for x, y in zip(xs, ys)]
+    ss = sum((y - my) ** 2 for y in ys)
+    return a, b, 1 - sum(r * r for r in res) / ss, max(abs(r) / y for r, y in zip(res, ys))
+
+
+def summarize_sweep(root):
+    """Table 1's N-sweep at 1920x1024 (forward kernel times against N) with a
+    linear fit per variant."""
+    d = _json_lines(root, "sweep")[-1]
+    rows = d["rows"]
+    cmd = "timeout -k 10 300 python3 bench.py --sweep > <out>/sweep.log"
+    lines = ["# Table 1 N-sweep: forward kernel at 1920x1024 against N", "",
+             "Command (from the repository root on an MI355X machine), then `python bench.py "
+             "--summarize sweep <out>`:", "", "```", cmd, "```", "",
+             "Forward kernel time per launch (mean of 10 launches after a warm-up, HIP events "
+             "around the kernel) for the seeded paper-shaped cloud of each N (x U[0,1920), "
+             "y U[0,1024), z U[0.5,1] m, A U[0.5,1]).  The HD5850 column is the paper's Table 1 "
+             "(its recurrence kernel on other hardware): context, not a target.  G/s = "
+             "N x 1920 x 1024 / t.", "",
+             "| N | HD5850 (paper) ms | plain ms | plain G/s | recurrence ms | recurrence G/s | "
+             "compensated ms | compensated G/s | recurrence / paper speed-up |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        paper = r.get("paper_hd5850_ms")
+        lines.append("| %d | %s | %.3f | %.0f | %.3f | %.0f | %.3f | %.0f | %s |" % (
+            r["n"], paper if paper else "-", r["plain_ms"], r["plain_gpps"], r["recurrence_ms"],
+            r["recurrence_gpps"], r["compensated_ms"], r["compensated_gpps"],
+            "%.0fx" % (paper / r["recurrence_ms"]) if paper else "-"))
+    lines += ["", "Linear fit t = a + b N over all rows (time is linear in N at a fixed "
+              "hologram, as in Table 1):", "",
+              "| variant | a (us) | b (ns per point) | R^2 | largest residual / t |",
+              "|---|---|---|---|---|"]
+    ns = [r["n"] for r in rows]
+    for v in ("plain", "recurrence", "compensated"):
+        a, b, r2, worst = _linear_fit(ns, [r[v + "_ms"] for r in rows])
+        lines.append("| %s | %.1f | %.2f | %.6f | %.2f%% |" % (v, a * 1e3, b * 1e6, r2,
+                                                               100 * worst))
+    a, b, r2, worst = _linear_fit([r["n"] for r in rows if r.get("paper_hd5850_ms")],
+                                  [r["paper_hd5850_ms"] for r in rows if r.get("paper_hd5850_ms")])
+    lines += ["", "The paper's HD5850 column fits t = a + b N with a = %.1f ms and b = %.1f us "
+              "per point (R^2 = %.5f)." % (a, b * 1e3, r2)]
+    _write_md("sweep_1920x1024.md", lines)
+
+
+WORKLOAD_FILES = {"mesh8k": "workload_mesh8k_1920x1080.md",
+                  "mesh64k": "workload_mesh64k_1920x1080.md",
+                  "adjoint": "workload_adjoint_1024x1024.md",
+                  "fit4k": "workload_fit4k_3840x2160.md"}
+
+
+def summarize_workloads(root):
+    """One summary per workload report line (--workload W), and the oracle
+    timing (--oracle-timing), from the logs under root."""
+    for d in _json_lines(root, "workload"):
+        w = d["workload"]
+        cmd = "timeout -k 10 900 python3 bench.py --workload %s > <out>/workload_%s.log" % (w, w)
+        lines = ["# Workload %s: %dx%d hologram, N = %d" % (w, d["nx"], d["ny"], d["n_points"]),
+                 "", d["description"], "",
+                 "Command (from the repository root on an MI355X machine), then `python bench.py "
+                 "--summarize workloads <out>`:", "", "```", cmd, "```", "",
+                 "Kernel times are the mean of %d launches (HIP events around the kernel).  "
+                 "Errors are max |dI| / sum |A| against the FP64 GPU forward on the full grid.  "
+                 "Roofline fractions: of the FP32 vector peak for the direct variants (slots per "
+                 "interaction as in bench.py), of the matrix-core peak of the GEMM operand type "
+                 "for the separable ones; 'of mix' is the fraction of the same instruction mix run "
+                 "alone by the machine probe." % d["reps"], "",
+                 "FP64 GPU forward: %.2f ms (%.0f G interactions/s)." % (d["fwd_f64_ms"],
+                                                                        d["fwd_f64_gpps"]), "",
+                 "| variant | fwd ms | fwd G/s | fwd frac | fwd of mix | adj ms | adj G/s | "
+                 "adj frac | adj of mix | max err / sum|A| |",
+                 "|---|---|---|---|---|---|---|---|---|---|"]
+        for v in ALL_VARIANTS:
+            r = d.get(v)
+            if not r:
+                continue
+            fm, am = r.get("fwd_frac_of_mix"), r.get("adj_frac_of_mix")
+            if fm is None and mix_interactions("fwd_" + v):
+                fm = r["fwd_gpps"] * 1e9 / mix_interactions("fwd_" + v)
+            if am is None and mix_interactions("adj_" + v):
+                am = r["adj_gpps"] * 1e9 / mix_interactions("adj_" + v)
+            lines.append("| %s | %.4g | %.0f | %.2f | %s | %.4g | %.0f | %.2f | %s | %.2e |" % (
+                v, r["fwd_kernel_ms"], r["fwd_gpps"], r["fwd_roofline_frac"],
+                "%.2f" % fm if fm else "-", r["adj_kernel_ms"], r["adj_gpps"],
+                r["adj_roofline_frac"], "%.2f" % am if am else "-",
+                r["max_err_vs_fp64_over_sum_abs_a"]))
+        f = d.get("fit")
+        if f:
+            lines += ["", "## Fitting loop (%d Adam iterations, lr %g, %s)" % (
+                f["iterations"], f["lr"], f["params"]), "",
+                "- %.2f iterations/s (%.2f s in total)" % (f["iterations_per_s"], f["seconds"]),
+                "- loss %.4g -> %.4g (%.1f%%)" % (f["loss_first"], f["loss_last"],
+                                                   100 * (f["loss_last"] / f["loss_first"] - 1)),
+                "- in the loop: forward %.2f ms (%.0f G/s), adjoint %.2f ms (%.0f G/s)" % (
+                    f["fwd_kernel_ms"], f["fwd_gpps"], f["adj_kernel_ms"], f["adj_gpps"]),
+                "- fitted cloud's compensated hologram against FP64: max |dI| / sum |A| = %.2e" %
+                f["fitted_fwd_max_err_vs_fp64_over_sum_abs_a"], "",
+                "Loss curve (L = 0.5 ||I - T||^2 before each iteration):", "",
+                "| iteration | loss |", "|---|---|"]
+            lines += ["| %d | %.6g |" % (i, v) for i, v in enumerate(f["loss_curve"])]
+        _write_md(WORKLOAD_FILES.get(w, "workload_%s.md" % w), lines)
+    try:
+        o = _json_lines(root, "oracle_timing")[-1]
+    except SystemExit:
+        return
+    lines = ["# Oracle timing on the MI355X machine's host CPU", "",
+             "Command (from the repository root on an MI355X machine), then `python bench.py "
+             "--summarize workloads <out>`:", "", "```",
+             "timeout -k 10 900 python3 bench.py --oracle-timing > <out>/oracle_timing.log",
+             "```", "",
+             "CPU: %s, %d allowed cores.  Oracle: %s.  GPU: %s." % (
+                 o["cpu_model"], o["cores"], o["oracle"], o["gpu"]), "",
+             "| workload | what | threads | interactions | oracle s | oracle G/s | GPU G/s | "
+             "GPU / oracle |", "|---|---|---|---|---|---|---|---|"]
+    for r in o["rows"]:
+        lines.append("| %s | %s | %d | %.3g | %.3g | %.3g | %.0f | %.3g |" % (
+            r["workload"], r["what"], r["threads"], r["interactions"], r["seconds"],
+            r["oracle_gpps"], r["gpu_gpps"], r["gpu_over_oracle"]))
+    _write_md("oracle_timing.md", lines)
+
+
 def summarize(kind, root):
     fn = {"stats": summarize_stats, "traffic": summarize_traffic,
-          "counters": summarize_counters}.get(kind)
+          "counters": summarize_counters, "sweep": summarize_sweep,
+          "workloads": summarize_workloads}.get(kind)
     if fn is None:
-        raise SystemExit("--summarize KIND must be stats, traffic or counters")
+        raise SystemExit("--summarize KIND must be stats, traffic, counters, sweep or workloads")
     fn(root)
 
 

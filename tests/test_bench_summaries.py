@@ -177,3 +177,50 @@ def test_source_hash_ignores_comments_not_code(bench, tmp_path):
     assert bench._sources_hash(["k.hip"], str(tmp_path)) == h
     (tmp_path / "k.hip").write_text(src.replace("1.0f", "2.0f"))
     assert bench._sources_hash(["k.hip"], str(tmp_path)) != h
+
+
+def test_sweep_summary_fits_a_line(bench, tmp_path):
+    """Times exactly linear in N give R^2 = 1, zero residuals, and the
+    intercept and slope they were made from."""
+    run = tmp_path / "sweep"
+    run.mkdir()
+    rows = []
+    for n in (512, 1024, 2048, 4096):
+        rec = {"n": n, "paper_hd5850_ms": {512: 19, 1024: 31}.get(n)}
+        for v, (a, b) in {"plain": (0.01, 3.8e-4), "recurrence": (0.02, 2.6e-4),
+                          "compensated": (0.005, 2.3e-4)}.items():
+            rec[v + "_ms"] = a + b * n
+            rec[v + "_gpps"] = n * 1920 * 1024 / (rec[v + "_ms"] * 1e-3) / 1e9
+        rows.append(rec)
+    (run / "sweep.log").write_text("noise line\n" + json.dumps(
+        {"mode": "sweep", "hologram": "1920x1024", "rows": rows}) + "\n")
+    a, b, r2, worst = bench._linear_fit([r["n"] for r in rows], [r["plain_ms"] for r in rows])
+    assert a == pytest.approx(0.01) and b == pytest.approx(3.8e-4)
+    assert r2 == pytest.approx(1.0) and worst < 1e-12
+    bench.summarize("sweep", str(run))
+    text = open(os.path.join(bench.PROFILES, "sweep_1920x1024.md")).read()
+    assert "| compensated | 5.0 | 230.00 | 1.000000 | 0.00% |" in text
+    assert "| 512 | 19 |" in text and "| 4096 | - |" in text
+
+
+def test_workload_summary_tables_and_loss_curve(bench, tmp_path):
+    run = tmp_path / "wl"
+    run.mkdir()
+    r = {"fwd_kernel_ms": 2.0, "fwd_gpps": 8000.0, "fwd_roofline_frac": 0.61,
+         "fwd_frac_of_mix": 0.83, "adj_kernel_ms": 4.0, "adj_gpps": 4000.0,
+         "adj_roofline_frac": 0.6, "adj_frac_of_mix": None,
+         "max_err_vs_fp64_over_sum_abs_a": 1.5e-7}
+    line = {"mode": "workload", "workload": "fit4k", "description": "desc", "nx": 3840,
+            "ny": 2160, "n_points": 16384, "interactions": 1, "reps": 3, "fwd_f64_ms": 90.0,
+            "fwd_f64_gpps": 600.0, "compensated": r,
+            "fit": {"iterations": 3, "seconds": 0.1, "iterations_per_s": 30.0, "lr": 0.01,
+                    "params": "A and z/pitch", "loss_first": 4.0, "loss_last": 3.0,
+                    "loss_curve": [4.0, 3.5, 3.0], "fwd_kernel_ms": 14.0, "adj_kernel_ms": 28.0,
+                    "fwd_gpps": 9000.0, "adj_gpps": 4500.0,
+                    "fitted_fwd_max_err_vs_fp64_over_sum_abs_a": 2e-7}}
+    (run / "workload_fit4k.log").write_text(json.dumps(line) + "\n")
+    bench.summarize("workloads", str(run))
+    text = open(os.path.join(bench.PROFILES, "workload_fit4k_3840x2160.md")).read()
+    assert "| compensated | 2 | 8000 | 0.61 | 0.83 | 4 | 4000 | 0.60 | - | 1.50e-07 |" in text
+    assert "loss 4 -> 3 (-25.0%)" in text
+    assert "| 2 | 3 |" in text
