@@ -24,6 +24,21 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned i, unsigned n) {
   return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
 }
 
+// Wave priority by progress.  The SIMD arbiter issues the oldest ready wave
+// first, so the workgroups that share a CU from the launch on do not advance
+// together: the first finishes long before the last, which then runs with few
+// waves per SIMD.  A wave that starts at priority 3 and drops to 2, 1 and 0 as
+// it passes each quarter of its loop yields to the waves behind it, so the
+// workgroups of a CU finish close together.  Scheduling only: results do not
+// change.  priority_step(i, n) is called at step i of a loop whose counter
+// steps by one through [0, n).
+__device__ __forceinline__ void priority_start() { __builtin_amdgcn_s_setprio(3); }
+__device__ __forceinline__ void priority_step(int i, int n) {
+  if (i == n / 4) __builtin_amdgcn_s_setprio(2);
+  if (i == n / 2) __builtin_amdgcn_s_setprio(1);
+  if (i == 3 * n / 4) __builtin_amdgcn_s_setprio(0);
+}
+
 // Workgroups of `threads` covering `count` items on a 1-D grid, or 0 when
 // that exceeds the grid's x limit (2^31 - 1); launchers then return
 // hipErrorInvalidValue instead of launching a truncated grid.

@@ -260,7 +260,9 @@ __device__ __forceinline__ void fwd_comp_body(const float* __restrict__ xrec,
 #pragma unroll
   for (int i = 0; i < kCompRows; ++i) acc[i] = 0.0f;
   load_tile(0);
+  priority_start();
   for (int t = 0; t < ntiles; ++t) {
+    priority_step(t, ntiles);
     if (t > 0) __syncthreads();  // every wave is done with the previous tile
     store_tile();
     __syncthreads();
