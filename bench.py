@@ -848,15 +848,15 @@ def summarize_stats(root):
 # the algorithmic bytes of one launch at the headline workload.
 TRAFFIC_KERNELS = {
     "adj_partial_kernel<1>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"],
-                              "G 7.86 MB + row table 8.39 MB (read once per strip: 60x) + "
-                              "inputs 0.02 MB + run partials 8.39 MB (512 runs)"),
+                              "G 7.86 MB + row table 8.39 MB + column table 7.86 MB + "
+                              "inputs 0.02 MB + run partials 8.39 MB (512 runs) = 32.5 MB"),
     "adj_partial_kernel<0>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"],
                               "G 7.86 MB + inputs 0.02 MB + run partials 8.39 MB (512 runs)"),
     "adj_partial_kernel<2>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"],
                               "G 7.86 MB + inputs 0.02 MB + run partials 8.39 MB (512 runs)"),
     "fwd_comp_kernel": (["forward.hip", "phase.h", "cgh_internal.h"],
-                        "row table 4.19 MB + column table 7.86 MB (read once per row block: "
-                        "32x) + amplitudes + hologram 7.86 MB"),
+                        "row table 4.19 MB + column table 7.86 MB + amplitudes + "
+                        "hologram 7.86 MB = 19.9 MB"),
     "fwd_plain_kernel": (["forward.hip", "phase.h", "cgh_internal.h"],
                          "records 0.02 MB + hologram 7.86 MB"),
     "fwd_rec_kernel<8, 4, 2>": (["forward.hip", "phase.h", "cgh_internal.h"],
@@ -1014,12 +1014,13 @@ COUNTER_PASSES = (
     "SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_MFMA SQ_VALU_MFMA_BUSY_CYCLES "
     "GRBM_GUI_ACTIVE GRBM_COUNT",
 )
-# Direct kernels per variant, with the algorithmic (instructions, of which
-# transcendental, issue slots) per interaction.
+# Direct kernels per variant, with the roofline key of their algorithmic work
+# per interaction (FP32_OPS + TRANS_OPS instructions).
 COUNTER_KERNELS = {
-    "compensated": {"fwd_comp_kernel": (3, 1, 4), "adj_partial_kernel<1>": (6, 2, 8)},
-    "plain": {"fwd_plain_kernel": (6, 1, 7), "adj_partial_kernel<0>": (8, 2, 10)},
-    "recurrence": {"fwd_rec_kernel<8, 4, 2>": (3, 1, 4), "adj_partial_kernel<2>": (6, 2, 8)},
+    "compensated": {"fwd_comp_kernel": "fwd_compensated", "adj_partial_kernel<1>": "adj_compensated"},
+    "plain": {"fwd_plain_kernel": "fwd_plain", "adj_partial_kernel<0>": "adj_plain"},
+    "recurrence": {"fwd_rec_kernel<8, 4, 2>": "fwd_recurrence",
+                   "adj_partial_kernel<2>": "adj_recurrence"},
 }
 
 
@@ -1053,12 +1054,15 @@ def summarize_counters(root):
               "Counter values are averages over the kernel's dispatches.  SQ_INSTS_* count wave "
               "instructions (64 lanes each) over the chip; GRBM_GUI_ACTIVE is summed over the 8 "
               "XCDs; VALU busy is 4 SQ_ACTIVE_INST_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE / 8).", "",
-              "Per point-pixel interaction (N nx ny = %d; lanes that compute padding count):" % n,
-              "", "| kernel | VALU instr | of which transcendental | algorithmic instr (slots) | "
-              "issued slots (trans = 2) | VALU busy | SALU / VALU | SMEM / VALU | LDS / VALU |",
+              "Per point-pixel interaction (N nx ny = %d; lanes that compute padding count).  "
+              "Algorithmic: the FP32 operations and transcendentals the roofline counts; "
+              "slots: FP32 ops + 4 per transcendental (quarter rate) of the FP32 vector peak."
+              % n, "", "| kernel | VALU instr | of which transcendental | algorithmic instr "
+              "(of which transcendental) | algorithmic slots | VALU busy | SALU / VALU | "
+              "SMEM / VALU | LDS / VALU |",
               "|---|---|---|---|---|---|---|---|---|"]
     for v, ks in COUNTER_KERNELS.items():
-        for k, (ins, _, slots) in ks.items():
+        for k, key in ks.items():
             c = data[v].get(k)
             if c is None:
                 print("no counters for", k)
@@ -1066,8 +1070,9 @@ def summarize_counters(root):
             valu = c["SQ_INSTS_VALU"] * 64 / n
             tr = c["SQ_INSTS_VALU_TRANS_F32"] * 64 / n
             busy = 4 * c["SQ_ACTIVE_INST_VALU"] / (1024 * c["GRBM_GUI_ACTIVE"] / 8)
-            lines.append("| `%s` | %.2f | %.2f | %d (%d) | %.2f | %.0f%% | %.3f | %.4f | %.4f |" % (
-                k, valu, tr, ins, slots, valu + tr, 100 * busy,
+            lines.append("| `%s` | %.2f | %.2f | %d (%d) | %d | %.0f%% | %.3f | %.4f | %.4f |" % (
+                k, valu, tr, FP32_OPS[key] + TRANS_OPS[key], TRANS_OPS[key], SLOTS[key],
+                100 * busy,
                 c["SQ_INSTS_SALU"] / c["SQ_INSTS_VALU"], c["SQ_INSTS_SMEM"] / c["SQ_INSTS_VALU"],
                 c["SQ_INSTS_LDS"] / c["SQ_INSTS_VALU"]))
     g = data["separable_f16x3"].get("gemm_half_kernel<2>")

@@ -128,9 +128,10 @@ def test_counter_summary_per_interaction(bench, tmp_path):
     bench.summarize("counters", str(run))
     with open(os.path.join(bench.PROFILES, "counters_paper_1920x1024_n1024.md")) as f:
         text = f.read()
-    # 4 VALU and 1 transcendental per interaction: 5 issued slots; VALU busy 50%
-    assert "| `fwd_comp_kernel` | 4.00 | 1.00 | 3 (4) | 5.00 | 50% | 0.250 | 0.0250 | 0.0000 |" in text
-    assert "| `adj_partial_kernel<2>` | 4.00 | 1.00 | 6 (8) | 5.00 | 50% |" in text
+    # 4 VALU (1 transcendental) per interaction against the algorithmic 3 (1):
+    # 2 FP32 ops + 4 slots for the cosine = 6 slots; VALU busy 50%
+    assert "| `fwd_comp_kernel` | 4.00 | 1.00 | 3 (1) | 6 | 50% | 0.250 | 0.0250 | 0.0000 |" in text
+    assert "| `adj_partial_kernel<2>` | 4.00 | 1.00 | 6 (2) | 12 | 50% |" in text
     assert "| 100 | 32.0 |" in text  # MFMA per dispatch, busy cycles per MFMA
 
 
