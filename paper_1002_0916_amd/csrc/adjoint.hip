@@ -51,12 +51,12 @@ template <int KIND>
 __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
     const float* __restrict__ a, int64_t n, double pitch, double wavelength,
-    const float* __restrict__ g, int64_t ldg, int ny, int64_t strip_rows, int npad,
-    const float2* __restrict__ rtab, const float* __restrict__ ctab,
+    const float* __restrict__ g, int64_t ldg, int ny, int64_t strip_rows, AdjOrder order,
+    int npad, const float2* __restrict__ rtab, const float* __restrict__ ctab,
     float4* __restrict__ partial) {
   constexpr bool kComp = KIND == kAdjCompensated || KIND == kAdjCompensatedInline;
-  // Neighbouring runs and all point groups of a run share G: keep them on
-  // one XCD.
+  // Neighbouring runs and all point groups of a run share G and the tables:
+  // keep them on one XCD.
   const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int run = (int)(tile / gridDim.y);
   const int j = (int)(tile % gridDim.y) * kWave + threadIdx.x;
@@ -155,11 +155,18 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     Sr = __builtin_fmaf(dy2, sr, Sr);
   };
 
-  // The run, one strip segment at a time (a run crosses at most a few strips).
+  // The run, one strip segment at a time: the strip-rows of one strip within
+  // one block of the order (a run crosses at most a few).
   for (int64_t q = q0; q < q1;) {
-    const int strip = (int)(q / ny);
-    const int row0 = (int)(q - (int64_t)strip * ny);
-    row1 = (int)min((int64_t)ny, row0 + (q1 - q));
+    int beta = 0;
+    while (beta + 1 < kXcds && q >= order.off[beta + 1]) ++beta;
+    const int h = beta / order.B, b = beta - h * order.B;
+    const int r_lo = b * order.br;
+    const int rows_b = min(ny, r_lo + order.br) - r_lo;
+    const int64_t local = q - order.off[beta];
+    const int strip = h * order.sh + (int)(local / rows_b);
+    const int row0 = r_lo + (int)(local - (local / rows_b) * rows_b);
+    row1 = (int)min((int64_t)(r_lo + rows_b), row0 + (q1 - q));
     col0 = strip * kAdjCols;
     // Column terms: the compensated x-phase of each strip column, the
     // recurrence step delta_c, or dx.
@@ -329,7 +336,7 @@ hipError_t launch_adj_partial(const Plan& p, const Workspace& w, const float* x,
   const dim3 grid(runs, p.ngroups);
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, grid, dim3(kAdjThreads), 0, s, x, y, z, a, p.n, pitch, wavelength,
-                       g, ldg, p.ny, p.strip_rows, (int)p.npad, (const float2*)w.rtab,
+                       g, ldg, p.ny, p.strip_rows, p.adj_order, (int)p.npad, (const float2*)w.rtab,
                        (const float*)w.ctab, (float4*)w.partial);
   };
   if (p.adj_kind == kAdjCompensated) {

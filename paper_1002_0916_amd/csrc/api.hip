@@ -3,6 +3,7 @@
 // HIP-event timing of the main kernels.
 #include <math.h>
 
+#include <algorithm>
 #include <atomic>
 #include <map>
 #include <mutex>
@@ -137,6 +138,28 @@ Plan make_plan(int64_t n, int32_t nx, int32_t ny, int32_t variant, int32_t op,
                                            : kAdjPlain;
   p.nsx = (int32_t)ceil_div(nx, kAdjCols);
   p.strip_rows = (int64_t)p.nsx * ny;
+  {
+    int best_h = 1;
+    double best = 0.0;
+    for (int h = 1; h <= kXcds; h *= 2) {
+      const double bytes = (double)h * ny * 8.0 + (double)(kXcds / h) * p.nsx * kAdjCols * 4.0;
+      if (h == 1 || bytes < best) {
+        best = bytes;
+        best_h = h;
+      }
+    }
+    AdjOrder& o = p.adj_order;
+    o.B = kXcds / best_h;
+    o.sh = (int)ceil_div(p.nsx, best_h);
+    o.br = (int)ceil_div(ny, o.B);
+    o.off[0] = 0;
+    for (int beta = 0; beta < kXcds; ++beta) {
+      const int h = beta / o.B, b = beta % o.B;
+      const int64_t strips = std::max<int64_t>(0, std::min<int64_t>(p.nsx, (int64_t)(h + 1) * o.sh) - (int64_t)h * o.sh);
+      const int64_t rows = std::max<int64_t>(0, std::min<int64_t>(ny, (int64_t)(b + 1) * o.br) - (int64_t)b * o.br);
+      o.off[beta + 1] = o.off[beta] + strips * rows;
+    }
+  }
   int64_t runs = ceil_div(kAdjMaxWaves, p.ngroups);
   const int64_t max_runs = ceil_div(p.strip_rows, kAdjMinRun);
   if (runs > max_runs) runs = max_runs;

@@ -142,6 +142,20 @@ constexpr int kFinSlices = 16;
 constexpr int kAdjFinPoints = 16;
 constexpr int kAdjFinSlices = 64;
 
+// The adjoint's order of strip-rows.  The (strip, row) space is cut into
+// kXcds blocks, H strip groups x B row bands (H B = kXcds): block
+// beta = h B + b covers strips [h sh, min(nsx, (h + 1) sh)) and rows
+// [b br, min(ny, (b + 1) br)), strip-major inside, and off[beta] is its first
+// index in the order (off[kXcds] = nsx ny).  Runs are equal ranges of this
+// order and xcd_tile places consecutive runs on one XCD, so each XCD works
+// through about one block: it reads only its band of the row table and its
+// strips' share of the column table.  H is chosen to minimise the bytes the
+// XCDs read between them: H row tables and B column tables.
+struct AdjOrder {
+  int64_t off[kXcds + 1];
+  int sh, br, B;
+};
+
 // Point records, all produced on the device by the prep kernel from the FP32
 // inputs with FP64 arithmetic.
 //
@@ -196,6 +210,7 @@ struct Plan {
   // partial buffer holds; the launch may use fewer)
   int32_t nsx, regions, ngroups, adj_kind;
   int64_t strip_rows;
+  AdjOrder adj_order;
   bool need_gpad;
   // separable variant
   int32_t nxp, nyp, sep_splits, sep_splits_u, sep_splits_p;

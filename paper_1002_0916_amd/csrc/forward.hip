@@ -208,8 +208,11 @@ __device__ __forceinline__ void fwd_comp_body(const float* __restrict__ xrec,
   __shared__ float4 as4[kTile / 4];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  // Tiles in column-major order, so each XCD takes a band of columns: it
+  // reads only its columns' share of the column table (the larger table),
+  // and all of the row table.
   const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  const int bx = (int)(tile % gridDim.x), by = (int)(tile / gridDim.x);
+  const int by = (int)(tile % gridDim.y), bx = (int)(tile / gridDim.y);
   const int col = bx * kWave + lane;
   const int col0 = bx * kWave;
   const int grp = by * kCompWaves + wave;
