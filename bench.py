@@ -643,7 +643,7 @@ def report_workload(args):
     torch.cuda.synchronize()
     out["fwd_f64_ms"] = (time.perf_counter() - t64) * 1e3
     out["fwd_f64_gpps"] = inter / (out["fwd_f64_ms"] * 1e-3) / 1e9
-    for variant in ALL_VARIANTS:
+    for variant in ((args.variant,) if args.only else ALL_VARIANTS):
         fk, ak = FWD_KERNEL[variant], ADJ_KERNEL[variant]
         Iv = B.forward(x, y, z, a, nx, ny, wl.pitch, wl.wavelength, variant)
         err = float((Iv.double() - I64).abs().max().item()) / suma
@@ -667,7 +667,7 @@ def report_workload(args):
                                 if mix_interactions("adj_" + variant) else None),
             "max_err_vs_fp64_over_sum_abs_a": err,
         }
-    if args.workload == "fit4k":
+    if args.workload == "fit4k" and args.fit_iters > 0:
         from paper_1002_0916_amd import fit as F
 
         hx, hy, hz, ha = (torch.from_numpy(v).to(dev) for v in hidden.astuple())
@@ -1008,6 +1008,52 @@ def summarize_traffic(root):
 RDREQ_COUNTERS = ("TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum "
                   "TCC_EA0_RDREQ_sum")
 
+# Algorithmic bytes of one launch of the compensated kernels at 3840x2160,
+# N = 16384 (npad 16384): tables of FP32 per (row or column, point).
+FIT4K_ALGORITHMIC = {
+    "fwd_comp_kernel": (2160 * 16384 * 4 + 3840 * 16384 * 4 + 2160 * 3840 * 4,
+                        "row table 141.6 MB + column table 251.7 MB + hologram 33.2 MB"),
+    "adj_partial_kernel<1>": (2160 * 3840 * 4 + 2160 * 16384 * 8 + 3840 * 16384 * 4
+                              + 32 * 16384 * 16,
+                              "G 33.2 MB + row table 283.1 MB + column table 251.7 MB + "
+                              "run partials 8.4 MB (32 runs)"),
+}
+
+
+def summarize_traffic_fit4k(root):
+    """HBM bytes per launch of the compensated kernels at 3840x2160, N=16384
+    (copy-calibrated FETCH_SIZE and WRITE_SIZE of `bench.py --workload fit4k
+    --only --fit-iters 0`)."""
+    copy_bytes = 268435456
+    fe = _counter_means(_csv_files(os.path.join(root, "fetch"), "*counter_collection.csv"))
+    wr = _counter_means(_csv_files(os.path.join(root, "write"), "*counter_collection.csv"))
+    cf = _counter_means(_csv_files(os.path.join(root, "copy_fetch"), "*counter_collection.csv"))
+    cw = _counter_means(_csv_files(os.path.join(root, "copy_write"), "*counter_collection.csv"))
+    ff = cf["__amd_rocclr_copyBuffer"]["FETCH_SIZE"] * 1024 / copy_bytes
+    wf = cw["__amd_rocclr_copyBuffer"]["WRITE_SIZE"] * 1024 / copy_bytes
+    cmd = "bench.py --workload fit4k --only --variant compensated --fit-iters 0"
+    lines = ["# HBM traffic per launch: compensated kernels at 3840x2160, N=16384", "",
+             "Commands (from the repository root on an MI355X machine, one counter per run), then "
+             "`python bench.py --summarize traffic_fit4k <out>`:", "", "```",
+             _ROCPROF.rstrip(" &")]
+    for d, counter, c in (("fetch", "FETCH_SIZE", cmd), ("write", "WRITE_SIZE", cmd),
+                          ("copy_fetch", "FETCH_SIZE", "bench.py --copy-bytes %d" % copy_bytes),
+                          ("copy_write", "WRITE_SIZE", "bench.py --copy-bytes %d" % copy_bytes)):
+        lines.append("timeout -s KILL 300 rocprofv3 --kernel-trace --pmc %s -f csv -d <out>/%s "
+                     "-o %s -- python3 %s" % (counter, d, d, c))
+    lines += ["```", "", "Copy calibration as for the 1920x1024 record: bytes = FETCH_SIZE x 1024 "
+              "/ %.5f and WRITE_SIZE x 1024 / %.3f." % (ff, wf), "",
+              "| kernel | fetch | write | total | algorithmic bytes | total / algorithmic |",
+              "|---|---|---|---|---|---|"]
+    for k, (alg, what) in FIT4K_ALGORITHMIC.items():
+        if k not in fe or k not in wr:
+            print("no counters for", k)
+            continue
+        f, w = fe[k]["FETCH_SIZE"] * 1024 / ff, wr[k]["WRITE_SIZE"] * 1024 / wf
+        lines.append("| %s | %.1f MB | %.1f MB | %.1f MB | %s = %.1f MB | %.2f |" % (
+            k, f / 1e6, w / 1e6, (f + w) / 1e6, what, alg / 1e6, (f + w) / alg))
+    _write_md("traffic_fit4k_3840x2160_n16384.md", lines)
+
 COUNTER_PASSES = (
     "SQ_INSTS_VALU SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_SALU SQ_INSTS_SMEM SQ_INSTS_LDS SQ_WAVES "
     "GRBM_GUI_ACTIVE",
@@ -1240,10 +1286,11 @@ def summarize_workloads(root):
 
 def summarize(kind, root):
     fn = {"stats": summarize_stats, "traffic": summarize_traffic,
-          "counters": summarize_counters, "sweep": summarize_sweep,
-          "workloads": summarize_workloads}.get(kind)
+          "traffic_fit4k": summarize_traffic_fit4k, "counters": summarize_counters,
+          "sweep": summarize_sweep, "workloads": summarize_workloads}.get(kind)
     if fn is None:
-        raise SystemExit("--summarize KIND must be stats, traffic, counters, sweep or workloads")
+        raise SystemExit("--summarize KIND must be stats, traffic, traffic_fit4k, counters, "
+                         "sweep or workloads")
     fn(root)
 
 
