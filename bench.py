@@ -54,20 +54,23 @@ TRANS_SLOTS = 4
 #                   rows of a lane; seeds are overhead)     (+ cos)
 #  adj plain        r2 (fma), Prev*r2, fract, Sc fma, G*sin folded into the
 #                   column and row sums (2 fma)             (+ sin, cos)
-#  adj compensated  X+Y add, Sc fma, column/row sums (2)    (+ sin, cos)
+#  adj compensated  sin and cos of X+Y from the per-axis cosines and sines by
+#                   the addition theorem (2 mul, 2 fma), Sc fma, column/row
+#                   sums (2 fma); no transcendental per interaction
 #  adj recurrence   Gamma += delta_c, Sc fma, column/row sums (2) (+ sin, cos)
 FP32_OPS = {"fwd_plain": 5, "fwd_compensated": 2, "fwd_recurrence": 2,
-            "adj_plain": 6, "adj_compensated": 4, "adj_recurrence": 4}
+            "adj_plain": 6, "adj_compensated": 7, "adj_recurrence": 4}
 TRANS_OPS = {"fwd_plain": 1, "fwd_compensated": 1, "fwd_recurrence": 1,
-             "adj_plain": 2, "adj_compensated": 2, "adj_recurrence": 2}
+             "adj_plain": 2, "adj_compensated": 0, "adj_recurrence": 2}
 SLOTS = {k: FP32_OPS[k] + TRANS_SLOTS * TRANS_OPS[k] for k in FP32_OPS}
 # The practical ceiling: each kernel's per-interaction instruction mix run
-# alone by the probe (issue-bound, 16 waves per SIMD, operands where the
-# kernel holds them), in CU clocks per 64 interactions.  The recurrence
-# adjoint issues the compensated adjoint's mix (an add of two VGPRs, sine,
-# cosine, three FMAs with G from an SGPR).
-MIX_CLOCKS = {"fwd_plain": 6.097, "fwd_compensated": 3.695, "adj_plain": 9.281,
-              "adj_compensated": 7.878, "adj_recurrence": 7.878}
+# alone by the probe (issue-bound, 8 resident waves per SIMD, operands where
+# the kernel holds them), in CU clocks per 64 interactions.  The recurrence
+# adjoint issues an add of two VGPRs, sine, cosine and three FMAs with G from
+# an SGPR; the compensated adjoint two products, two FMAs (sin and cos by the
+# addition theorem) and the same three FMAs.
+MIX_CLOCKS = {"fwd_plain": 6.083, "fwd_compensated": 3.680, "adj_plain": 9.285,
+              "adj_compensated": 4.088, "adj_recurrence": 7.823}
 CU_CLOCKS_PER_S = 256 * 2.4e9
 # The separable variant is a different algorithm, bound by the FP32 matrix
 # cores (dense MFMA FP32 peak 157.3 TFLOP/s): the forward is one GEMM of

@@ -15,13 +15,20 @@
 // r^2 = dx^2 + dy^2, so per strip the lane keeps the column phases (or dx, or
 // the recurrence steps) and the column sums of G sin(theta) in registers, and
 // per row it takes the row phase (or dy^2) once and folds the row sum of
-// G sin(theta) with dy and dy^2.  The compensated kind reads the row phase
-// and dy from a row table (one 8-byte load per row and lane) and the strip's
-// column phases from a column table (one 4-byte load per column and lane per
-// strip segment), both built once per call, instead of forming them in every
-// strip.
-// Per interaction that leaves the phase, sin and cos, and three fused
-// multiply-adds with G taken straight from an SGPR.
+// G sin(theta) with dy and dy^2.
+// The compensated kinds split the phase by axis, theta = X + Y (the
+// compensated column and row phases), and take sin(theta) and cos(theta) from
+// the per-axis cosines and sines by the addition theorem,
+//   sin(X + Y) = sX cY + cX sY,   cos(X + Y) = cX cY - sX sY,
+// an exact identity: per strip the lane keeps cX, sX of its columns, per row
+// cY, sY, and per interaction that leaves two products and two fused
+// multiply-adds for sin and cos (no transcendental) and three fused
+// multiply-adds with G taken straight from an SGPR.  The compensated kind
+// reads cY and sY from a row table (one 8-byte load per row and lane) and the
+// strip's column phases from a column table (one 4-byte load per column and
+// lane per strip segment), both built once per call, instead of forming them
+// in every strip.  The plain and recurrence kinds take sin and cos of each
+// interaction's phase on the transcendental unit.
 //
 // Second pass: kAdjFinSlices threads per point add interleaved subsets of
 // the region partials in region order, then one thread adds the slice sums in
@@ -39,7 +46,7 @@ namespace cgh {
 
 namespace {
 
-// KIND: kAdjPlain, kAdjCompensated (row phases and dy from the row table,
+// KIND: kAdjPlain, kAdjCompensated (the rows' cY, sY from the row table,
 // column phases from the column table), kAdjCompensatedInline (the same
 // values formed here) or kAdjRecurrence.  With the recurrence
 // (Eq. (2), Section 2.1) each strip row starts from the plain phase
@@ -71,7 +78,9 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
   const float yc = rec.yc, yph = rec.ph, ypl = rec.pl, yb = rec.yb, yd = rec.yd;
 
   float Sc0 = 0.f, Sc1 = 0.f, Sx = 0.f, Sy = 0.f, Sr = 0.f;
-  float CX[kAdjCols], SgC[kAdjCols];
+  // CX: the strip's column terms (compensated kinds: the cosine of the
+  // column phase, SX its sine); SgC: column sums of G sin(theta).
+  float CX[kAdjCols], SX[kAdjCols], SgC[kAdjCols];
   int col0 = 0, row1 = 0;
   float dx0sq = 0.f;  // recurrence: (x_h - x_j)^2 at the strip's first column
 
@@ -85,8 +94,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
 #pragma unroll
     for (int k = 0; k < kAdjCols; ++k) dst[k] = src[k];
   };
-  // The compensated kind's {y-phase, dy} of a row, from the row table (one
-  // 8-byte load per lane, issued a row ahead like G).
+  // The compensated kind's {cY, sY} of a row, from the row table (one 8-byte
+  // load per lane, issued a row ahead like G).
   // A buffer load: the row's byte offset (at most kAdjRowTabMaxBytes) is a
   // scalar operand and the lane's offset a 32-bit vector one, so forming the
   // address costs no vector instruction; the descriptor bounds the table.
@@ -107,18 +116,21 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     return make_float2(v.x, v.y);
   };
   auto do_row = [&](int row, const float* gc, float* gn, float2 rc, float2& rn) {
-    float dy, RY;
-    if (KIND == kAdjCompensated) {
-      RY = rc.x;
-      dy = rc.y;
-    } else {
-      const float yh = (float)row;
-      dy = yh - py;
-      RY = KIND == kAdjCompensatedInline ? axis_phase(yh, yc, yph, ypl, yb, yd) : 0.f;
-    }
+    const float dy = (float)row - py;
     const float dy2 = dy * dy;
-    if (KIND == kAdjPlain) RY = dy2;
+    // Plain: dy^2; recurrence: the row's starting phase.
+    const float RY = KIND == kAdjPlain ? dy2 : 0.f;
     float gam = KIND == kAdjRecurrence ? fract(prev * (dx0sq + dy2)) : 0.f;
+    // Compensated kinds: the cosine and sine of the row phase.
+    float cY = 0.f, sY = 0.f;
+    if (KIND == kAdjCompensated) {
+      cY = rc.x;
+      sY = rc.y;
+    } else if (KIND == kAdjCompensatedInline) {
+      const float ry = axis_phase((float)row, yc, yph, ypl, yb, yd);
+      cY = cos_rev(ry);
+      sY = sin_rev(ry);
+    }
     float sr0 = 0.f, sr1 = 0.f;
 #pragma unroll
     for (int c = 0; c < kAdjCols; ++c) {
@@ -130,17 +142,22 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
         __builtin_amdgcn_sched_barrier(0);
       }
       const float G = gc[c];
-      float t;
+      float s, co;
       if (kComp) {
-        t = CX[c] + RY;
-      } else if (KIND == kAdjRecurrence) {
-        t = gam;
-        gam += CX[c];
+        // sin and cos of X + Y by the addition theorem
+        s = __builtin_fmaf(SX[c], cY, CX[c] * sY);
+        co = __builtin_fmaf(CX[c], cY, -(SX[c] * sY));
       } else {
-        t = fract(prev * __builtin_fmaf(CX[c], CX[c], RY));
+        float t;
+        if (KIND == kAdjRecurrence) {
+          t = gam;
+          gam += CX[c];
+        } else {
+          t = fract(prev * __builtin_fmaf(CX[c], CX[c], RY));
+        }
+        s = sin_rev(t);
+        co = cos_rev(t);
       }
-      const float s = sin_rev(t);
-      const float co = cos_rev(t);
       if (c & 1) {
         Sc1 = __builtin_fmaf(G, co, Sc1);
         sr1 = __builtin_fmaf(G, s, sr1);
@@ -184,6 +201,13 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
       else
         CX[c] = h - px;
       SgC[c] = 0.f;
+    }
+    if (kComp) {
+#pragma unroll
+      for (int c = 0; c < kAdjCols; ++c) {
+        SX[c] = sin_rev(CX[c]);
+        CX[c] = cos_rev(CX[c]);
+      }
     }
     if (KIND == kAdjRecurrence) {
       const float dx0 = (float)col0 - px;

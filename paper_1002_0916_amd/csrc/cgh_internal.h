@@ -110,8 +110,8 @@ static_assert(kPointPad % (2 * kRecUnroll) == 0, "point padding holds whole grou
 constexpr int kAdjCols = 32;
 // Phase arithmetic of the adjoint kernel (Plan::adj_kind): the plain FP32
 // phase, the compensated axis phases, or the recurrence of Eq. (2) along the
-// strip row.  The compensated kind reads each row's y-phase and dy from a
-// table [ny][npad] and each strip column's x-phase from a table
+// strip row.  The compensated kind reads the cosine and sine of each row's
+// y-phase from a table [ny][npad] and each strip column's x-phase from a table
 // [nsx * kAdjCols][npad], both built by one precompute launch (the same
 // values it would form itself, once per row or column and point instead of
 // once per strip and point); when either table would exceed
@@ -125,15 +125,16 @@ constexpr int64_t kAdjRowTabMaxBytes = int64_t(512) << 20;
 constexpr int kAdjThreads = kWave;
 // At launch the number of runs is chosen so that kAdjRounds rounds of
 // resident waves (CUs x resident waves per CU, from the occupancy query)
-// cover the whole hologram with equal work per wave.  The partial-sum buffer is sized for at
-// most kAdjMaxWaves waves (256 CUs x 4 SIMDs x 8) and runs hold at least
-// kAdjMinRun strip-rows.
-constexpr int kAdjMaxWaves = 256 * 4 * 8;
-constexpr int kAdjMinRun = 8;
+// cover the whole hologram with equal work per wave, and runs hold at least
+// kAdjMinRun strip-rows.  The partial-sum buffer is sized for kAdjRounds
+// rounds at up to 8 resident waves per SIMD on 256 CUs (kAdjMaxWaves), so
+// the last round is never cut short at any occupancy a kernel reaches.
 #ifndef CGH_ADJ_ROUNDS
 #define CGH_ADJ_ROUNDS 3
 #endif
 constexpr int kAdjRounds = CGH_ADJ_ROUNDS;
+constexpr int kAdjMaxWaves = kAdjRounds * 256 * 4 * 8;
+constexpr int kAdjMinRun = 8;
 // Second passes: kFinSlices threads per point add interleaved subsets of the
 // partial planes (the separable finalize), and the direct adjoint's finalize
 // spreads its many run partials over kAdjFinSlices threads for each of
@@ -179,7 +180,7 @@ struct Workspace {
   double4* rec64;  // [npad]
   float* ytab;     // forward, compensated: [groups][npad][kCompRows]
   float* xtab;     // forward, compensated (optional): [fwd_gx * 64][npad] x-phases
-  float2* rtab;    // adjoint, compensated: [ny][npad] {y-phase, y_h - y_j}
+  float2* rtab;    // adjoint, compensated: [ny][npad] {cos, sin of the y-phase}
   float* ctab;     // adjoint, compensated: [nsx * kAdjCols][npad] x-phases
   float* partial;  // adjoint: [regions][npad][4]
   float* gpad;     // adjoint: G copied to a [ny][nsx*kAdjCols] zero-padded grid
@@ -242,8 +243,9 @@ hipError_t launch_prep_ytab(const float* x, const float* y, const float* z, cons
                             double pitch, double wavelength, const Plan& p, const Workspace& w,
                             hipStream_t s);
 // The compensated adjoint's tables, from the FP32 inputs in one launch: for
-// every row y_h and point j the compensated y-phase of y_h and y_h - y_j, and
-// for every strip column x_h and point j the compensated x-phase of x_h.
+// every row y_h and point j the cosine and sine of the compensated y-phase of
+// y_h, and for every strip column x_h and point j the compensated x-phase of
+// x_h.
 hipError_t launch_prep_rtab(const float* x, const float* y, const float* z, const float* a,
                             double pitch, double wavelength, const Plan& p, const Workspace& w,
                             hipStream_t s);

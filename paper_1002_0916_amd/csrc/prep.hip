@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void prep_ytab_kernel(
 
 // The compensated adjoint's tables: thread (g, j) forms point j's records
 // and, for g < groups, writes for the kRtabRows rows y_h of row group g
-//   rtab[y_h][j] = {axis_phase(y_h) of point j, y_h - y_j};
+//   rtab[y_h][j] = {cos, sin of axis_phase(y_h) of point j};
 // the threads after those write, for the kRtabRows columns x_h of column
 // group g - groups (columns up to the last strip's end),
 //   ctab[x_h][j] = axis_phase(x_h) of point j:
@@ -111,8 +111,8 @@ __global__ __launch_bounds__(256) void prep_rtab_kernel(
     const int rows = min(kRtabRows, ny - row0);
     for (int i = 0; i < rows; ++i) {
       const float yh = (float)(row0 + i);
-      rtab[(int64_t)(row0 + i) * npad + j] =
-          make_float2(axis_phase(yh, r.yc, r.ph, r.pl, r.yb, r.yd), yh - r.y);
+      const float ry = axis_phase(yh, r.yc, r.ph, r.pl, r.yb, r.yd);
+      rtab[(int64_t)(row0 + i) * npad + j] = make_float2(cos_rev(ry), sin_rev(ry));
     }
   } else {
     const int64_t c0 = (g - groups) * kRtabRows;

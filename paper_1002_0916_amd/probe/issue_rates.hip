@@ -6,9 +6,11 @@
 // accuracy of v_cos_f32 / v_sin_f32 (cos and sin of 2 pi t) against the
 // host's FP64 libm.
 //
-// Rates: workgroups of 256 threads (4096 of them: 16 waves per SIMD, or 2048:
-// 8), each thread running 8 independent dependency chains for 4096 steps, so
-// the measurement is issue-bound, not latency-bound.  A step of a mixed mode
+// Rates: workgroups of 256 threads (one wave per SIMD each), 16, 8, 4, 3 or 2
+// of them per CU, each thread running 8 independent dependency chains for
+// 4096 steps, so the measurement is issue-bound, not latency-bound; the last
+// column is the most waves per SIMD that a mode's register use lets be
+// resident (a launch of more runs in rounds).  A step of a mixed mode
 // issues one instruction of each listed kind per chain.  Values that are
 // wave-uniform in the kernels (a, b) are SGPR operands; av, bv hold the same
 // values in VGPRs (0 * t is not folded under strict FP).  Best of 4 launches.
@@ -28,7 +30,7 @@
   } while (0)
 
 constexpr int kChains = 8;
-constexpr int kModes = 16;
+constexpr int kModes = 19;
 const char* const kNames[kModes] = {
     "fma (v, s, s)",  "fma (v, v, v)",   "add (v, s)",        "add (v, v)",
     "fract",          "cos",             "sin",               "cos + sin",
@@ -38,20 +40,34 @@ const char* const kNames[kModes] = {
     "fwd plain: sub, fma, mul, fract, cos, fma (point in SGPRs)",
     "adj compensated: add, sin, cos, 3 fma (G in SGPR)",
     "adj compensated: add, sin, cos, 3 fma (G in VGPR)",
-    "adj plain: fma, mul, fract, sin, cos, 3 fma (G in SGPR)"};
+    "adj plain: fma, mul, fract, sin, cos, 3 fma (G in SGPR)",
+    "adj addition: 2 mul, 2 fma, 3 fma (G in SGPR)",
+    "adj factored sums: 4 fma (G in SGPR)",
+    "adj factored sums: 4 fma (G in VGPR)"};
+
+// Eight distinct wave-uniform values (SGPRs, from the kernel arguments).
+struct Uniform {
+  float g[kChains];
+};
 
 template <int MODE>
-__global__ void rate(float* out, int iters, float a, float b) {
+__global__ void rate(float* out, int iters, float a, float b, Uniform u) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const float av = __builtin_fmaf(0.0f, (float)t, a), bv = __builtin_fmaf(0.0f, (float)t, b);
-  float x[kChains], y[kChains], s0[kChains], s1[kChains], s2[kChains];
+  float x[kChains], y[kChains], s0[kChains], s1[kChains], s2[kChains], s3[kChains], gv[kChains];
 #pragma unroll
   for (int k = 0; k < kChains; ++k) {
     x[k] = 0.001f * (t + k);
     y[k] = 0.002f * (t - k);
-    s0[k] = s1[k] = s2[k] = 0.0f;
+    s0[k] = s1[k] = s2[k] = s3[k] = 0.0f;
+    gv[k] = __builtin_fmaf(0.0f, (float)t, u.g[k]);
   }
+  // Per-step values of modes 16-18 (a row's cosine and sine), so their
+  // products stay in the loop.
+  float bw = bv, cw = av;
   for (int it = 0; it < iters; ++it) {
+    if (MODE >= 16) bw = bw + a;
+    if (MODE >= 17) cw = cw + b;
 #pragma unroll
     for (int k = 0; k < kChains; ++k) {
       if (MODE == 0) x[k] = __builtin_fmaf(x[k], a, b);
@@ -95,6 +111,20 @@ __global__ void rate(float* out, int iters, float a, float b) {
         s2[k] = __builtin_fmaf(g, sn, s2[k]);
         x[k] = tt;
       }
+      if (MODE == 16) {  // sin, cos of X + Y from per-axis (cX, sX), (cY, sY); 3 sums
+        const float sn = __builtin_fmaf(y[k], av, x[k] * bw);
+        const float cs = __builtin_fmaf(x[k], av, -(y[k] * bw));
+        s0[k] = __builtin_fmaf(a, cs, s0[k]);
+        s1[k] = __builtin_fmaf(a, sn, s1[k]);
+        s2[k] = __builtin_fmaf(a, sn, s2[k]);
+      }
+      if (MODE == 17 || MODE == 18) {  // row sums of G cX, G sX; column sums of G cY, G sY
+        const float g = MODE == 17 ? u.g[k] : gv[k];
+        s0[k] = __builtin_fmaf(g, x[k], s0[k]);
+        s1[k] = __builtin_fmaf(g, y[k], s1[k]);
+        s2[k] = __builtin_fmaf(g, cw, s2[k]);
+        s3[k] = __builtin_fmaf(g, bw, s3[k]);
+      }
       if (MODE == 15) {  // fract(Prev (dx^2 + RY)), sin, cos, 3 sums
         const float tt = __builtin_amdgcn_fractf(bv * __builtin_fmaf(x[k], x[k], y[k]));
         const float sn = __builtin_amdgcn_sinf(tt), cs = __builtin_amdgcn_cosf(tt);
@@ -107,19 +137,95 @@ __global__ void rate(float* out, int iters, float a, float b) {
   }
   float s = 0.f;
 #pragma unroll
-  for (int k = 0; k < kChains; ++k) s += x[k] + y[k] + s0[k] + s1[k] + s2[k];
+  for (int k = 0; k < kChains; ++k) s += x[k] + y[k] + s0[k] + s1[k] + s2[k] + s3[k];
   out[t] = s;  // keeps every chain live
+}
+
+// The compensated adjoint's row body as the kernel runs it: 32 columns, each
+// taking sin and cos of X + Y by the addition theorem from the column's (cX,
+// sX) and the row's (cY, sY), then three sums with G from SGPRs (the point's
+// two row-sum chains, its row sum of G sin split in two, and the column sum).
+// LOADG = false: G of every row from the kernel arguments; true: G of row r
+// from a 64-row table in memory through two scalar loads per row, issued a
+// row ahead into ping-pong buffers as the kernel does.
+constexpr int kRowCols = 32;
+struct RowG {
+  float g[kRowCols];
+};
+template <bool LOADG>
+__global__ void adj_row(float* out, int iters, float a, float b, RowG u, const float* gtab) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  float CX[kRowCols], SX[kRowCols], SgC[kRowCols];
+#pragma unroll
+  for (int c = 0; c < kRowCols; ++c) {
+    CX[c] = 0.001f * (t + c);
+    SX[c] = 0.002f * (t - c);
+    SgC[c] = 0.0f;
+  }
+  float cY = __builtin_fmaf(0.0f, (float)t, a), sY = __builtin_fmaf(0.0f, (float)t, b);
+  float Sc0 = 0.f, Sc1 = 0.f, Sy = 0.f, Sr = 0.f;
+  float gA[kRowCols], gB[kRowCols];
+#pragma unroll
+  for (int c = 0; c < kRowCols; ++c) gA[c] = LOADG ? gtab[c] : u.g[c];
+  auto row = [&](int it, const float* gc, float* gn) {
+    cY = cY + a;
+    sY = sY + b;
+    float sr0 = 0.f, sr1 = 0.f;
+#pragma unroll
+    for (int c = 0; c < kRowCols; ++c) {
+      if (LOADG && c == 1) {
+        __builtin_amdgcn_sched_barrier(0);
+        const float* src = gtab + ((it + 1) & 63) * kRowCols;
+#pragma unroll
+        for (int k = 0; k < kRowCols; ++k) gn[k] = src[k];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      const float G = LOADG ? gc[c] : u.g[c];
+      const float sn = __builtin_fmaf(SX[c], cY, CX[c] * sY);
+      const float cs = __builtin_fmaf(CX[c], cY, -(SX[c] * sY));
+      if (c & 1) {
+        Sc1 = __builtin_fmaf(G, cs, Sc1);
+        sr1 = __builtin_fmaf(G, sn, sr1);
+      } else {
+        Sc0 = __builtin_fmaf(G, cs, Sc0);
+        sr0 = __builtin_fmaf(G, sn, sr0);
+      }
+      SgC[c] = __builtin_fmaf(G, sn, SgC[c]);
+    }
+    const float sr = sr0 + sr1;
+    Sy = __builtin_fmaf(cY, sr, Sy);
+    Sr = __builtin_fmaf(sY, sr, Sr);
+  };
+  for (int it = 0; it < iters; it += 2) {
+    row(it, gA, gB);
+    row(it + 1, gB, gA);
+  }
+  float s = Sc0 + Sc1 + Sy + Sr;
+#pragma unroll
+  for (int c = 0; c < kRowCols; ++c) s += SgC[c];
+  out[t] = s;
 }
 
 template <int M>
 void launch(int blocks, float* d, int iters) {
-  rate<M><<<blocks, 256>>>(d, iters, 1.0001f, 0.5f);
+  Uniform u;
+  for (int k = 0; k < kChains; ++k) u.g[k] = 0.25f + 0.125f * k;
+  rate<M><<<blocks, 256>>>(d, iters, 1.0001f, 0.5f, u);
+}
+
+template <int M>
+int resident(void) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, rate<M>, 256, 0) != hipSuccess) return -1;
+  return blocks;
 }
 
 typedef void (*Launch)(int, float*, int);
+typedef int (*Resident)(void);
 template <int... M>
 struct Table {
   static constexpr Launch fns[] = {launch<M>...};
+  static constexpr Resident res[] = {resident<M>...};
 };
 
 __global__ void trig(const float* in, float* oc, float* os, int n) {
@@ -137,19 +243,25 @@ int main() {
          p.gcnArchName);
   const int iters = 4096;
   float* d;
-  CK(hipMalloc(&d, sizeof(float) * 4096 * 256));
+  CK(hipMalloc(&d, sizeof(float) * 16 * p.multiProcessorCount * 256));
   hipEvent_t e0, e1;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
-  const Launch* fns = Table<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15>::fns;
+  typedef Table<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18> Modes;
+  const Launch* fns = Modes::fns;
   // One 64-lane instruction per CU per clock.
   const double per_cycle = (double)p.multiProcessorCount * 64 * (p.clockRate * 1e3);
   printf("\ncycles per step (one 64-lane instruction per CU per clock = 1)\n");
-  printf("%-60s %10s %10s\n", "step", "16 waves", "8 waves");
+  // Workgroups of 4 waves, one per SIMD: 4096 of them give 16 waves per SIMD.
+  const int kWaves[] = {16, 8, 4, 3, 2};
+  constexpr int kCols = sizeof(kWaves) / sizeof(kWaves[0]);
+  printf("%-56s", "step (waves per SIMD)");
+  for (int w = 0; w < kCols; ++w) printf(" %7d", kWaves[w]);
+  printf(" %7s\n", "max");
   for (int mode = 0; mode < kModes; ++mode) {
-    double cyc[2];
-    for (int w = 0; w < 2; ++w) {
-      const int blocks = w == 0 ? 4096 : 2048;
+    double cyc[kCols];
+    for (int w = 0; w < kCols; ++w) {
+      const int blocks = kWaves[w] * p.multiProcessorCount;
       float best = 1e30f;
       for (int rep = 0; rep < 4; ++rep) {
         CK(hipEventRecord(e0));
@@ -164,7 +276,57 @@ int main() {
       const double steps = (double)blocks * 256 * iters * kChains;
       cyc[w] = per_cycle * best * 1e-3 / steps;
     }
-    printf("%-60s %10.3f %10.3f\n", kNames[mode], cyc[0], cyc[1]);
+    printf("%-56s", kNames[mode]);
+    for (int w = 0; w < kCols; ++w) printf(" %7.3f", cyc[w]);
+    printf(" %7d\n", Modes::res[mode]());
+  }
+
+  // The adjoint's row body: cycles per interaction (per column of a row).
+  {
+    RowG u;
+    for (int c = 0; c < kRowCols; ++c) u.g[c] = 0.25f + 0.0625f * c;
+    float* gtab;
+    CK(hipMalloc(&gtab, sizeof(float) * 64 * kRowCols));
+    std::vector<float> hg(64 * kRowCols);
+    for (size_t i = 0; i < hg.size(); ++i) hg[i] = 0.25f + 0.001f * (float)i;
+    CK(hipMemcpy(gtab, hg.data(), sizeof(float) * hg.size(), hipMemcpyHostToDevice));
+    // Configurations: G from the kernel arguments or by scalar loads, in
+    // workgroups of 4 waves or of one wave (as the adjoint launches them).
+    for (int cfg = 0; cfg < 3; ++cfg) {
+      const int load = cfg > 0, threads = cfg == 2 ? 64 : 256;
+      double cyc[kCols];
+      for (int w = 0; w < kCols; ++w) {
+        const int blocks = kWaves[w] * p.multiProcessorCount * (256 / threads);
+        float best = 1e30f;
+        for (int rep = 0; rep < 4; ++rep) {
+          CK(hipEventRecord(e0));
+          if (load)
+            adj_row<true><<<blocks, threads>>>(d, iters / 4, 1e-7f, 2e-7f, u, gtab);
+          else
+            adj_row<false><<<blocks, threads>>>(d, iters / 4, 1e-7f, 2e-7f, u, gtab);
+          CK(hipGetLastError());
+          CK(hipEventRecord(e1));
+          CK(hipEventSynchronize(e1));
+          float ms;
+          CK(hipEventElapsedTime(&ms, e0, e1));
+          if (ms < best) best = ms;
+        }
+        const double steps = (double)blocks * threads * (iters / 4) * kRowCols;
+        cyc[w] = per_cycle * best * 1e-3 / steps;
+      }
+      int res = 0;
+      if (load)
+        CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&res, adj_row<true>, threads, 0));
+      else
+        CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&res, adj_row<false>, threads, 0));
+      res = res * threads / 256;
+      printf("%-56s", cfg == 0   ? "adj addition row, 32 columns (G in kernel args)"
+                      : cfg == 1 ? "adj addition row, 32 columns (G by scalar loads)"
+                                 : "  the same, one-wave workgroups");
+      for (int w = 0; w < kCols; ++w) printf(" %7.3f", cyc[w]);
+      printf(" %7d\n", res);
+    }
+    CK(hipFree(gtab));
   }
 
   // Accuracy of cos(2 pi t) and sin(2 pi t) over 2^24 points of each range.
