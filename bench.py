@@ -129,6 +129,10 @@ def parse():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the benchmark, run 5 plain device-to-device copies of this "
                          "many bytes (a known-traffic reference for hardware byte counters)")
+    ap.add_argument("--library-gemm", action="store_true",
+                    help="instead of the benchmark, time the platform's GEMM (torch.matmul: "
+                         "hipBLASLt / rocBLAS) at the separable variants' contraction shapes of "
+                         "the headline workload")
     ap.add_argument("--summarize", nargs=2, metavar=("KIND", "DIR"),
                     help="no GPU: write the profiles/ summary of KIND (stats, traffic or "
                          "counters) from the rocprofv3 CSV output under DIR")
@@ -223,6 +227,50 @@ def timed_steps(step, steps, torch):
     return e0.elapsed_time(e1) / steps, wall
 
 
+# The separable variants' contractions at the headline workload (1920x1024,
+# N = 1024: 2N = 2048 table columns), as (name, M, N, K) of C[M][N] =
+# sum_k A(m, k) B(n, k), and the library kernel each one is compared with:
+# this library's GEMM instantiation per operand format (fp16 hi/lo as one
+# plain fp16 GEMM of three times the depth: [Ah Ah Al] . [Bh Bl Bh]).
+SEP_GEMMS = (("forward I = Y X^T", 1024, 1920, 2048, 0),
+             ("adjoint U, K = rows", 2048, 1920, 1024, 1),
+             ("adjoint P, K = columns", 2048, 1024, 1920, 2))
+SEP_OURS = {"f32": "gemm_f32_kernel<%s>", "f16": "gemm_half_kernel<0, %d>",
+            "bf16": "gemm_half_kernel<1, %d>", "f16x3": "gemm_half_kernel<2, %d>"}
+SEP_F32_ARGS = {0: "true, true, 0", 1: "false, false, 1", 2: "false, true, 2"}
+
+
+def library_gemm():
+    """torch.matmul (the platform's GEMM library) at the separable contraction
+    shapes: mean of 50 launches after 5 warm-up ones, by CUDA events on
+    torch's stream (one matmul per launch, so launch gaps are included)."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = []
+    for name, m, n, k, fold in SEP_GEMMS:
+        for fmt, dt, depth in (("f32", torch.float32, k), ("f16", torch.float16, k),
+                               ("bf16", torch.bfloat16, k), ("f16x3", torch.float16, 3 * k)):
+            g = torch.Generator(device=dev).manual_seed(7)
+            A = torch.randn(m, depth, device=dev, generator=g).to(dt)
+            Bt = torch.randn(depth, n, device=dev, generator=g).to(dt)
+            C = torch.empty(m, n, device=dev, dtype=dt)
+            for _ in range(5):
+                torch.matmul(A, Bt, out=C)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(50):
+                torch.matmul(A, Bt, out=C)
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) / 50 * 1e3
+            out.append({"gemm": name, "format": fmt, "M": m, "N": n, "K": k, "depth": depth,
+                        "us": us, "flops": 2.0 * m * n * depth, "fold": fold})
+    print(json.dumps({"mode": "library_gemm", "torch": torch.__version__, "results": out}),
+          flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -236,6 +284,9 @@ def main():
         return
     if args.copy_bytes > 0:
         copy_reference(args.copy_bytes)
+        return
+    if args.library_gemm:
+        library_gemm()
         return
     if args.sweep:
         report_sweep(args)
@@ -1287,13 +1338,60 @@ def summarize_workloads(root):
     _write_md("oracle_timing.md", lines)
 
 
+def summarize_library(root):
+    """This library's GEMM kernels (average durations from the kernel-stats
+    run of the default benchmark, ROOT/stats) against the platform's GEMM at
+    the same contraction shapes (ROOT/library.log, `bench.py --library-gemm`)."""
+    import csv
+
+    lib = _json_lines(root, "library_gemm")[-1]
+    ours = {}
+    for f in _csv_files(os.path.join(root, "stats"), "*kernel_stats.csv"):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                ours[_kernel_short(r["Name"])] = float(r["AverageNs"]) / 1e3
+    lines = ["# The separable GEMMs against the platform's GEMM library, 1920x1024, N = 1024",
+             "", "Commands (from the repository root on an MI355X machine): the kernel-stats run "
+             "of the default benchmark (`profiles/bench_paper_1920x1024_n1024_kernel_stats.md`) "
+             "for this library's kernels, and", "", "```",
+             "timeout -k 10 300 python3 bench.py --library-gemm > <out>/library.log", "```", "",
+             "then `python bench.py --summarize library <out>`.  The platform's GEMM is "
+             "`torch.matmul` (torch %s: hipBLASLt / rocBLAS), timed by events over 50 launches "
+             "(launch gaps included, so its figures are upper bounds on its kernel time), on "
+             "plain operands of the same shape: its output is in the operand type and has no "
+             "epilogue, while this library's kernels write FP32 and the adjoint ones fold "
+             "their output per point in the epilogue.  fp16 hi/lo runs as one fp16 GEMM of "
+             "three times the depth.  Rates in TFLOP/s of the format's work (f16x3: three "
+             "products); %% of the dense peak (FP32 157.3 TFLOP/s, fp16/bf16 2.5 PFLOP/s)."
+             % lib["torch"], "",
+             "| contraction (M x N x K) | format | library us | library TFLOP/s | % peak | "
+             "this library us | TFLOP/s | % peak | speed-up |", "|---|---|---|---|---|---|---|---|---|"]
+    for r in lib["results"]:
+        peak = 157.3e12 if r["format"] == "f32" else 2.5e15
+        key = SEP_OURS[r["format"]] % (SEP_F32_ARGS[r["fold"]] if r["format"] == "f32"
+                                       else r["fold"])
+        mine = ours.get(key)
+        lt = r["flops"] / (r["us"] * 1e-6)
+        row = "| %s (%d x %d x %d) | %s | %.1f | %.0f | %.1f%% |" % (
+            r["gemm"], r["M"], r["N"], r["K"], r["format"], r["us"], lt / 1e12, 100 * lt / peak)
+        if mine:
+            mt = r["flops"] / (mine * 1e-6)
+            row += " %.1f | %.0f | %.1f%% | %.2fx |" % (mine, mt / 1e12, 100 * mt / peak,
+                                                      r["us"] / mine)
+        else:
+            row += " - | - | - | - |"
+        lines.append(row)
+    _write_md("gemm_library_comparison_1920x1024.md", lines)
+
+
 def summarize(kind, root):
     fn = {"stats": summarize_stats, "traffic": summarize_traffic,
           "traffic_fit4k": summarize_traffic_fit4k, "counters": summarize_counters,
-          "sweep": summarize_sweep, "workloads": summarize_workloads}.get(kind)
+          "sweep": summarize_sweep, "workloads": summarize_workloads,
+          "library": summarize_library}.get(kind)
     if fn is None:
         raise SystemExit("--summarize KIND must be stats, traffic, traffic_fit4k, counters, "
-                         "sweep or workloads")
+                         "sweep, workloads or library")
     fn(root)
 
 

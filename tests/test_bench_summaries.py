@@ -228,3 +228,33 @@ def test_workload_summary_tables_and_loss_curve(bench, tmp_path):
     assert "| compensated | 2 | 8000 | 0.61 | 0.83 | 4 | 4000 | 0.60 | 0.42 | 1.50e-07 |" in text
     assert "loss 4 -> 3 (-25.0%)" in text
     assert "| 2 | 3 |" in text
+
+
+def test_library_gemm_summary_matches_kernels_by_format_and_fold(bench, tmp_path):
+    run = tmp_path / "lib"
+    (run / "stats").mkdir(parents=True)
+    with open(run / "stats" / "bench_kernel_stats.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs",
+                    "MaxNs"])
+        w.writerow(["void cgh::(anonymous namespace)::gemm_half_kernel<2, 0>(unsigned short "
+                    "const*)", 10, 330000, 33000.0, 1.0, 32000, 34000])
+        w.writerow(["void cgh::(anonymous namespace)::gemm_f32_kernel<false, true, 2>(float "
+                    "const*)", 10, 800000, 80000.0, 1.0, 79000, 81000])
+    res = [{"gemm": "forward I = Y X^T", "format": "f16x3", "M": 1024, "N": 1920, "K": 2048,
+            "depth": 6144, "us": 48.0, "flops": 2.0 * 1024 * 1920 * 6144, "fold": 0},
+           {"gemm": "adjoint P, K = columns", "format": "f32", "M": 2048, "N": 1024,
+            "K": 1920, "depth": 1920, "us": 60.0, "flops": 2.0 * 2048 * 1024 * 1920, "fold": 2},
+           {"gemm": "adjoint P, K = columns", "format": "bf16", "M": 2048, "N": 1024,
+            "K": 1920, "depth": 1920, "us": 20.0, "flops": 2.0 * 2048 * 1024 * 1920, "fold": 2}]
+    (run / "library.log").write_text(json.dumps({"mode": "library_gemm", "torch": "x",
+                                                 "results": res}) + "\n")
+    bench.summarize("library", str(run))
+    text = open(os.path.join(bench.PROFILES, "gemm_library_comparison_1920x1024.md")).read()
+    # f16x3: 24.2 GFLOP in 48 us = 503 TFLOP/s (20.1% of 2.5 PF); ours 33 us: 732, 1.45x
+    assert "| forward I = Y X^T (1024 x 1920 x 2048) | f16x3 | 48.0 | 503 | 20.1% | 33.0 | 732 " \
+           "| 29.3% | 1.45x |" in text
+    # FP32 against the FP32 peak; P's FP32 kernel is <false, true, 2>
+    assert "| f32 | 60.0 | 134 | 85.3% | 80.0 | 101 | 64.0% | 0.75x |" in text
+    # a format with no kernel in the stats run gets dashes
+    assert "| bf16 | 20.0 | 403 | 16.1% | - | - | - | - |" in text
