@@ -903,11 +903,13 @@ def summarize_stats(root):
 TRAFFIC_KERNELS = {
     "adj_partial_kernel<1>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"],
                               "G 7.86 MB + row table 8.39 MB + column table 7.86 MB + "
-                              "inputs 0.02 MB + run partials 8.39 MB (512 runs) = 32.5 MB"),
+                              "inputs 0.02 MB + run partials 9.44 MB (576 runs: three rounds "
+                              "of 3 waves per SIMD over 16 point groups) = 33.6 MB"),
     "adj_partial_kernel<0>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"],
-                              "G 7.86 MB + inputs 0.02 MB + run partials 8.39 MB (512 runs)"),
+                              "G 7.86 MB + inputs 0.02 MB + run partials 12.58 MB (768 runs: "
+                              "4 waves per SIMD)"),
     "adj_partial_kernel<2>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"],
-                              "G 7.86 MB + inputs 0.02 MB + run partials 8.39 MB (512 runs)"),
+                              "G 7.86 MB + inputs 0.02 MB + run partials 9.44 MB (576 runs)"),
     "fwd_comp_kernel": (["forward.hip", "phase.h", "cgh_internal.h"],
                         "row table 4.19 MB + column table 7.86 MB + amplitudes + "
                         "hologram 7.86 MB = 19.9 MB"),
@@ -1068,9 +1070,10 @@ FIT4K_ALGORITHMIC = {
     "fwd_comp_kernel": (2160 * 16384 * 4 + 3840 * 16384 * 4 + 2160 * 3840 * 4,
                         "row table 141.6 MB + column table 251.7 MB + hologram 33.2 MB"),
     "adj_partial_kernel<1>": (2160 * 3840 * 4 + 2160 * 16384 * 8 + 3840 * 16384 * 4
-                              + 32 * 16384 * 16,
+                              + 36 * 16384 * 16,
                               "G 33.2 MB + row table 283.1 MB + column table 251.7 MB + "
-                              "run partials 8.4 MB (32 runs)"),
+                              "run partials 9.4 MB (36 runs: three rounds of 3 waves per SIMD "
+                              "over 256 point groups)"),
 }
 
 
@@ -1126,7 +1129,7 @@ COUNTER_KERNELS = {
 
 def summarize_counters(root):
     """Per-interaction VALU, transcendental, SALU, SMEM and LDS instruction
-    counts and VALU busy of the direct kernels, and matrix-core use of the
+    counts and VALU issue rate of the direct kernels, and matrix-core use of the
     fp16 hi/lo GEMM, from two counter passes per variant (DIR/<variant>.<pass>)."""
     variants = list(COUNTER_KERNELS) + ["separable_f16x3"]
     data = {}
@@ -1153,12 +1156,16 @@ def summarize_counters(root):
     lines += ["```", "",
               "Counter values are averages over the kernel's dispatches.  SQ_INSTS_* count wave "
               "instructions (64 lanes each) over the chip; GRBM_GUI_ACTIVE is summed over the 8 "
-              "XCDs; VALU busy is 4 SQ_ACTIVE_INST_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE / 8).", "",
+              "XCDs.  VALU issue is 4 SQ_ACTIVE_INST_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE / 8): "
+              "VALU instructions issued per SIMD per 4 clocks (a transcendental counting about "
+              "1.3).  One per 4 clocks (100%) is the single-issue rate; gfx950 issues FP32 "
+              "instructions whose operands are all VGPRs faster than that, so a kernel made of "
+              "them can exceed 100% (the machine probe: up to 1.6 per CU clock).", "",
               "Per point-pixel interaction (N nx ny = %d; lanes that compute padding count).  "
               "Algorithmic: the FP32 operations and transcendentals the roofline counts; "
               "slots: FP32 ops + 4 per transcendental (quarter rate) of the FP32 vector peak."
               % n, "", "| kernel | VALU instr | of which transcendental | algorithmic instr "
-              "(of which transcendental) | algorithmic slots | VALU busy | SALU / VALU | "
+              "(of which transcendental) | algorithmic slots | VALU issue | SALU / VALU | "
               "SMEM / VALU | LDS / VALU |",
               "|---|---|---|---|---|---|---|---|---|"]
     for v, ks in COUNTER_KERNELS.items():
