@@ -116,7 +116,8 @@ constexpr int kAdjCols = 32;
 // values it would form itself, once per row or column and point instead of
 // once per strip and point); when either table would exceed
 // kAdjRowTabMaxBytes the kernel forms them inline instead
-// (kAdjCompensatedInline, bitwise the same result).
+// (kAdjCompensatedInline: the same values, so the same result whenever the
+// launch takes the same run count; its lower occupancy can give it another).
 constexpr int kAdjPlain = 0;
 constexpr int kAdjCompensated = 1;
 constexpr int kAdjRecurrence = 2;

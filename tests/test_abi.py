@@ -113,7 +113,7 @@ def test_workspace_bytes(lib):
     rows_fit = 68 * 8 * 16384 * 4 * 4
     assert (f(*fit, B.COMPENSATED, B.OP_FORWARD) - f(*fit, B.PLAIN, B.OP_FORWARD)
             == rows_fit + 3840 * 16384 * 4)
-    # the compensated adjoint's tables: the row table, {y-phase, dy} per row
+    # the compensated adjoint's tables: the row table, {cos, sin} of the y-phase per row
     # and point (N * Ny float2), and the column table, the x-phase per strip
     # column and point (N * ceil(Nx / 32) * 32 floats), while each fits in
     # 512 MiB; above that the kernel forms the values itself and the
