@@ -30,7 +30,7 @@
   } while (0)
 
 constexpr int kChains = 8;
-constexpr int kModes = 19;
+constexpr int kModes = 21;
 const char* const kNames[kModes] = {
     "fma (v, s, s)",  "fma (v, v, v)",   "add (v, s)",        "add (v, v)",
     "fract",          "cos",             "sin",               "cos + sin",
@@ -43,7 +43,9 @@ const char* const kNames[kModes] = {
     "adj plain: fma, mul, fract, sin, cos, 3 fma (G in SGPR)",
     "adj addition: 2 mul, 2 fma, 3 fma (G in SGPR)",
     "adj factored sums: 4 fma (G in SGPR)",
-    "adj factored sums: 4 fma (G in VGPR)"};
+    "adj factored sums: 4 fma (G in VGPR)",
+    "fwd addition: mul, fma, fma (cY, sY, A in VGPRs)",
+    "fwd addition: mul, fma, fma (cY, sY, A in SGPRs)"};
 
 // Eight distinct wave-uniform values (SGPRs, from the kernel arguments).
 struct Uniform {
@@ -51,7 +53,8 @@ struct Uniform {
 };
 
 template <int MODE>
-__global__ void rate(float* out, int iters, float a, float b, Uniform u) {
+__global__ void rate(float* out, int iters, float a, float b, Uniform u,
+                     const float* __restrict__ tab) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const float av = __builtin_fmaf(0.0f, (float)t, a), bv = __builtin_fmaf(0.0f, (float)t, b);
   float x[kChains], y[kChains], s0[kChains], s1[kChains], s2[kChains], s3[kChains], gv[kChains];
@@ -125,6 +128,16 @@ __global__ void rate(float* out, int iters, float a, float b, Uniform u) {
         s2[k] = __builtin_fmaf(g, cw, s2[k]);
         s3[k] = __builtin_fmaf(g, bw, s3[k]);
       }
+      if (MODE == 19 || MODE == 20) {  // cos(X + Y) = cX cY - sX sY, acc += A cos
+        // x, y: the lane's (cX, sX), fixed per chain; the row's (cY, sY) change
+        // per step, in VGPRs (bw, cw) or SGPRs (from the table); A in a VGPR
+        // (av) or an SGPR (a)
+        // (mode 20: one row of a 64-row table per step, read by scalar loads)
+        const float* row = tab + (it & 63) * 16;
+        const float cy = MODE == 19 ? cw : row[k], sy = MODE == 19 ? bw : row[8 + k];
+        const float ct = __builtin_fmaf(x[k], cy, -(y[k] * sy));
+        s0[k] = __builtin_fmaf(MODE == 19 ? av : a, ct, s0[k]);
+      }
       if (MODE == 15) {  // fract(Prev (dx^2 + RY)), sin, cos, 3 sums
         const float tt = __builtin_amdgcn_fractf(bv * __builtin_fmaf(x[k], x[k], y[k]));
         const float sn = __builtin_amdgcn_sinf(tt), cs = __builtin_amdgcn_cosf(tt);
@@ -148,6 +161,56 @@ __global__ void rate(float* out, int iters, float a, float b, Uniform u) {
 // LOADG = false: G of every row from the kernel arguments; true: G of row r
 // from a 64-row table in memory through two scalar loads per row, issued a
 // row ahead into ping-pong buffers as the kernel does.
+// The compensated forward's addition-theorem step for a lane holding two
+// columns and two rows, with the row values (cos, sin of the row phases, A)
+// broadcast across the wave by DPP row_newbcast from a VGPR that holds them
+// once per 16-lane row: per point two moves (cY of each row) and one (A),
+// four products (sX sY, the broadcast folded into the product), four FMAs for
+// cos(X + Y) and four for the sums, i.e. 15 instructions per 4 interactions.
+// Cycles per interaction; 8 independent lane states per thread.
+template <int N>
+__device__ __forceinline__ float bcast(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + N, 0xf, 0xf, true));
+}
+__global__ void fwd_dpp(float* out, int iters, const float* __restrict__ tab) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  float cx[8][2], sx[8][2], acc[8][2][2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      cx[k][c] = 0.001f * (t + k + c);
+      sx[k][c] = 0.002f * (t - k + c);
+      acc[k][c][0] = acc[k][c][1] = 0.f;
+    }
+  // lane l of each 16-lane row holds value l of the current point's row data
+  float v = tab[threadIdx.x & 15];
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float a = bcast<4>(v);
+      const float cy[2] = {bcast<0>(v), bcast<1>(v)};
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const float m = sx[k][c] * (r ? bcast<3>(v) : bcast<2>(v));
+          const float ct = __builtin_fmaf(cx[k][c], cy[r], -m);
+          acc[k][c][r] = __builtin_fmaf(a, ct, acc[k][c][r]);
+        }
+      }
+      v = v + 1.0f;  // the next point's row data (one add per 4 interactions)
+    }
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) s += acc[k][c][0] + acc[k][c][1];
+  out[t] = s;
+}
+
 constexpr int kRowCols = 32;
 struct RowG {
   float g[kRowCols];
@@ -206,11 +269,14 @@ __global__ void adj_row(float* out, int iters, float a, float b, RowG u, const f
   out[t] = s;
 }
 
+// A 64-row table of 16 floats per row on the device (mode 20), set by main.
+const float* g_rowtab = nullptr;
+
 template <int M>
 void launch(int blocks, float* d, int iters) {
   Uniform u;
   for (int k = 0; k < kChains; ++k) u.g[k] = 0.25f + 0.125f * k;
-  rate<M><<<blocks, 256>>>(d, iters, 1.0001f, 0.5f, u);
+  rate<M><<<blocks, 256>>>(d, iters, 1.0001f, 0.5f, u, g_rowtab);
 }
 
 template <int M>
@@ -244,10 +310,18 @@ int main() {
   const int iters = 4096;
   float* d;
   CK(hipMalloc(&d, sizeof(float) * 16 * p.multiProcessorCount * 256));
+  {
+    float* t;
+    CK(hipMalloc(&t, sizeof(float) * 64 * 16));
+    std::vector<float> ht(64 * 16);
+    for (size_t i = 0; i < ht.size(); ++i) ht[i] = 0.5f + 0.001f * (float)i;
+    CK(hipMemcpy(t, ht.data(), sizeof(float) * ht.size(), hipMemcpyHostToDevice));
+    g_rowtab = t;
+  }
   hipEvent_t e0, e1;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
-  typedef Table<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18> Modes;
+  typedef Table<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20> Modes;
   const Launch* fns = Modes::fns;
   // One 64-lane instruction per CU per clock.
   const double per_cycle = (double)p.multiProcessorCount * 64 * (p.clockRate * 1e3);
@@ -327,6 +401,32 @@ int main() {
       printf(" %7d\n", res);
     }
     CK(hipFree(gtab));
+  }
+
+  // The forward's addition-theorem step with DPP row broadcasts.
+  {
+    double cyc[kCols];
+    for (int w = 0; w < kCols; ++w) {
+      const int blocks = kWaves[w] * p.multiProcessorCount;
+      float best = 1e30f;
+      for (int rep = 0; rep < 4; ++rep) {
+        CK(hipEventRecord(e0));
+        fwd_dpp<<<blocks, 256>>>(d, iters / 4, g_rowtab);
+        CK(hipGetLastError());
+        CK(hipEventRecord(e1));
+        CK(hipEventSynchronize(e1));
+        float ms;
+        CK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) best = ms;
+      }
+      const double steps = (double)blocks * 256 * (iters / 4) * 8 * 4;
+      cyc[w] = per_cycle * best * 1e-3 / steps;
+    }
+    int res = 0;
+    CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&res, fwd_dpp, 256, 0));
+    printf("%-56s", "fwd addition, 2x2 per lane, DPP row broadcasts");
+    for (int w = 0; w < kCols; ++w) printf(" %7.3f", cyc[w]);
+    printf(" %7d\n", res);
   }
 
   // Accuracy of cos(2 pi t) and sin(2 pi t) over 2^24 points of each range.
