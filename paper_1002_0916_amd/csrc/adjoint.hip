@@ -172,6 +172,16 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     Sr = __builtin_fmaf(dy2, sr, Sr);
   };
 
+  // Wave priority by progress (as in the forward), in the compensated kinds:
+  // 3 through the first quarter of the run's strip-rows, then 2, 1 and 0.
+  // The SIMD arbiter issues the oldest ready wave first, so without the steps
+  // the waves that share a SIMD finish far apart and the last runs alone;
+  // with them a wave that is behind takes the issue slots first.  Scheduling
+  // only: the sums do not change.  (The plain kind, at 4 waves per SIMD, was
+  // slower with the steps at 1920x1024; it and the recurrence keep the
+  // arbiter's order.)
+  int quarter = 0;
+  if (kComp) __builtin_amdgcn_s_setprio(3);
   // The run, one strip segment at a time: the strip-rows of one strip within
   // one block of the order (a run crosses at most a few).
   for (int64_t q = q0; q < q1;) {
@@ -218,9 +228,35 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     load_row(row0, gA);
     if (KIND == kAdjCompensated) rA = load_rtab(row0);
     int row = row0;
-    for (; row + 1 < row1; row += 2) {
-      do_row(row, gA, gB, rA, rB);
-      do_row(row + 1, gB, gA, rB, rA);
+    auto pairs = [&](int rend) {
+      for (; row + 1 < rend; row += 2) {
+        do_row(row, gA, gB, rA, rB);
+        do_row(row + 1, gB, gA, rB, rA);
+      }
+    };
+    if constexpr (kComp) {
+      // Row pairs up to the next quarter boundary of the run (rounded up to
+      // an even row offset, so the ping-pong buffers keep their parity), then
+      // one priority step, until the segment ends.
+      const int done = (int)(q - q0);
+      for (;;) {
+        int rend = row1;
+        if (quarter < 3) {
+          const int nb = (int)((int64_t)(quarter + 1) * (q1 - q0) / 4);
+          if (nb < done + (row1 - row0)) rend = min(row1, row0 + ((nb - done + 1) & ~1));
+        }
+        pairs(rend);
+        if (rend == row1) break;
+        ++quarter;
+        if (quarter == 1)
+          __builtin_amdgcn_s_setprio(2);
+        else if (quarter == 2)
+          __builtin_amdgcn_s_setprio(1);
+        else
+          __builtin_amdgcn_s_setprio(0);
+      }
+    } else {
+      pairs(row1);
     }
     if (row < row1) do_row(row, gA, gB, rA, rB);
 #pragma unroll

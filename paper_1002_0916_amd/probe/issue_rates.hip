@@ -10,12 +10,17 @@
 // of them per CU, each thread running 8 independent dependency chains for
 // 4096 steps, so the measurement is issue-bound, not latency-bound; the last
 // column is the most waves per SIMD that a mode's register use lets be
-// resident (a launch of more runs in rounds).  A step of a mixed mode
+// resident (a launch of more runs in rounds).  Cycles are counted at the
+// device's nominal clock (hipDeviceProp_t::clockRate); the GHz@16 column is
+// the shader clock measured in the 16-wave launch (median over workgroups of
+// the s_memtime count over the 100 MHz s_memrealtime count), which falls
+// below the nominal clock under a sustained VALU load.  A step of a mixed mode
 // issues one instruction of each listed kind per chain.  Values that are
 // wave-uniform in the kernels (a, b) are SGPR operands; av, bv hold the same
 // values in VGPRs (0 * t is not folded under strict FP).  Best of 4 launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -52,9 +57,33 @@ struct Uniform {
   float g[kChains];
 };
 
+// Shader clock during a launch: thread 0 of each workgroup stores the
+// shader-clock counter (s_memtime) and the constant 100 MHz counter
+// (s_memrealtime) at its start and replaces them by their increments at its
+// end; clock = ratio x 100 MHz.  The start values go through memory (the
+// barrier forces the reload), so they hold no register across the loop.
+__device__ __forceinline__ void clock_start(unsigned long long* clk) {
+  const unsigned long long c0 = __builtin_amdgcn_s_memtime();
+  const unsigned long long r0 = __builtin_amdgcn_s_memrealtime();
+  if (threadIdx.x == 0) {
+    clk[2 * blockIdx.x] = c0;
+    clk[2 * blockIdx.x + 1] = r0;
+  }
+}
+__device__ __forceinline__ void clock_end(unsigned long long* clk) {
+  __asm__ volatile("" ::: "memory");
+  const unsigned long long c1 = __builtin_amdgcn_s_memtime();
+  const unsigned long long r1 = __builtin_amdgcn_s_memrealtime();
+  if (threadIdx.x == 0) {
+    clk[2 * blockIdx.x] = c1 - clk[2 * blockIdx.x];
+    clk[2 * blockIdx.x + 1] = r1 - clk[2 * blockIdx.x + 1];
+  }
+}
+
 template <int MODE>
 __global__ void rate(float* out, int iters, float a, float b, Uniform u,
-                     const float* __restrict__ tab) {
+                     const float* __restrict__ tab, unsigned long long* clk) {
+  clock_start(clk);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const float av = __builtin_fmaf(0.0f, (float)t, a), bv = __builtin_fmaf(0.0f, (float)t, b);
   float x[kChains], y[kChains], s0[kChains], s1[kChains], s2[kChains], s3[kChains], gv[kChains];
@@ -152,6 +181,7 @@ __global__ void rate(float* out, int iters, float a, float b, Uniform u,
 #pragma unroll
   for (int k = 0; k < kChains; ++k) s += x[k] + y[k] + s0[k] + s1[k] + s2[k] + s3[k];
   out[t] = s;  // keeps every chain live
+  clock_end(clk);
 }
 
 // The compensated adjoint's row body as the kernel runs it: 32 columns, each
@@ -271,12 +301,26 @@ __global__ void adj_row(float* out, int iters, float a, float b, RowG u, const f
 
 // A 64-row table of 16 floats per row on the device (mode 20), set by main.
 const float* g_rowtab = nullptr;
+// Per-workgroup clock records (two counters each), sized by main for the
+// largest launch.
+unsigned long long* g_clk = nullptr;
+
+// Median shader clock in GHz over the workgroups of the last launch.
+double median_clock(int blocks) {
+  std::vector<unsigned long long> h(2 * (size_t)blocks);
+  if (hipMemcpy(h.data(), g_clk, h.size() * sizeof(h[0]), hipMemcpyDeviceToHost) != hipSuccess)
+    return -1.0;
+  std::vector<double> f(blocks);
+  for (int i = 0; i < blocks; ++i) f[i] = h[2 * i + 1] ? 0.1 * (double)h[2 * i] / h[2 * i + 1] : 0.0;
+  std::sort(f.begin(), f.end());
+  return f[blocks / 2];
+}
 
 template <int M>
 void launch(int blocks, float* d, int iters) {
   Uniform u;
   for (int k = 0; k < kChains; ++k) u.g[k] = 0.25f + 0.125f * k;
-  rate<M><<<blocks, 256>>>(d, iters, 1.0001f, 0.5f, u, g_rowtab);
+  rate<M><<<blocks, 256>>>(d, iters, 1.0001f, 0.5f, u, g_rowtab, g_clk);
 }
 
 template <int M>
@@ -318,6 +362,8 @@ int main() {
     CK(hipMemcpy(t, ht.data(), sizeof(float) * ht.size(), hipMemcpyHostToDevice));
     g_rowtab = t;
   }
+  // One record per workgroup of the largest rate launch.
+  CK(hipMalloc(&g_clk, sizeof(unsigned long long) * 2 * 16 * p.multiProcessorCount));
   hipEvent_t e0, e1;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
@@ -331,9 +377,9 @@ int main() {
   constexpr int kCols = sizeof(kWaves) / sizeof(kWaves[0]);
   printf("%-56s", "step (waves per SIMD)");
   for (int w = 0; w < kCols; ++w) printf(" %7d", kWaves[w]);
-  printf(" %7s\n", "max");
+  printf(" %7s %7s\n", "max", "GHz@16");
   for (int mode = 0; mode < kModes; ++mode) {
-    double cyc[kCols];
+    double cyc[kCols], ghz = 0.0;
     for (int w = 0; w < kCols; ++w) {
       const int blocks = kWaves[w] * p.multiProcessorCount;
       float best = 1e30f;
@@ -349,10 +395,11 @@ int main() {
       }
       const double steps = (double)blocks * 256 * iters * kChains;
       cyc[w] = per_cycle * best * 1e-3 / steps;
+      if (w == 0) ghz = median_clock(blocks);
     }
     printf("%-56s", kNames[mode]);
     for (int w = 0; w < kCols; ++w) printf(" %7.3f", cyc[w]);
-    printf(" %7d\n", Modes::res[mode]());
+    printf(" %7d %7.3f\n", Modes::res[mode](), ghz);
   }
 
   // The adjoint's row body: cycles per interaction (per column of a row).
@@ -398,7 +445,7 @@ int main() {
                       : cfg == 1 ? "adj addition row, 32 columns (G by scalar loads)"
                                  : "  the same, one-wave workgroups");
       for (int w = 0; w < kCols; ++w) printf(" %7.3f", cyc[w]);
-      printf(" %7d\n", res);
+      printf(" %7d %7s\n", res, "-");
     }
     CK(hipFree(gtab));
   }

@@ -223,9 +223,9 @@ def test_workload_summary_tables_and_loss_curve(bench, tmp_path):
     bench.summarize("workloads", str(run))
     text = open(os.path.join(bench.PROFILES, "workload_fit4k_3840x2160.md")).read()
     # a missing mix fraction is derived from the rate: 4000 G/s against the
-    # compensated adjoint's probe mix, 256 CUs x 2.4 GHz x 64 / 4.111 clocks
-    assert 4000e9 / bench.mix_interactions("adj_compensated") == pytest.approx(0.4181, abs=1e-4)
-    assert "| compensated | 2 | 8000 | 0.61 | 0.83 | 4 | 4000 | 0.60 | 0.42 | 1.50e-07 |" in text
+    # compensated adjoint's probe mix, 256 CUs x 2.4 GHz x 64 / 4.033 clocks
+    assert 4000e9 / bench.mix_interactions("adj_compensated") == pytest.approx(0.4103, abs=1e-4)
+    assert "| compensated | 2 | 8000 | 0.61 | 0.83 | 4 | 4000 | 0.60 | 0.41 | 1.50e-07 |" in text
     assert "loss 4 -> 3 (-25.0%)" in text
     assert "| 2 | 3 |" in text
 
