@@ -238,12 +238,13 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
       // Row pairs up to the next quarter boundary of the run (rounded up to
       // an even row offset, so the ping-pong buffers keep their parity), then
       // one priority step, until the segment ends.
-      const int done = (int)(q - q0);
+      const int64_t done = q - q0;
       for (;;) {
         int rend = row1;
         if (quarter < 3) {
-          const int nb = (int)((int64_t)(quarter + 1) * (q1 - q0) / 4);
-          if (nb < done + (row1 - row0)) rend = min(row1, row0 + ((nb - done + 1) & ~1));
+          const int64_t nb = (int64_t)(quarter + 1) * (q1 - q0) / 4;
+          // nb - done < row1 - row0 here, so the offset fits an int.
+          if (nb < done + (row1 - row0)) rend = min(row1, row0 + (int)((nb - done + 1) & ~int64_t(1)));
         }
         pairs(rend);
         if (rend == row1) break;
