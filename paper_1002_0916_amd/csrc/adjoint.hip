@@ -9,7 +9,9 @@
 // four per-point reductions over pixels runs inside one lane and no
 // cross-lane reduction is needed at all.  A wave takes 64 points and an equal
 // share (a run) of the strip-rows of the hologram, where a strip is kAdjCols
-// columns wide; kAdjRounds rounds of resident waves cover everything.  G is
+// columns wide; kAdjRounds rounds of resident waves cover everything (in the
+// compensated kinds each wave's priority steps down at the quarters of its
+// run, so the waves sharing a SIMD finish close together).  G is
 // wave-uniform and reaches the lanes through scalar loads, one strip row
 // (kAdjCols floats) at a time.  The pixel-dependent factors separate by axis,
 // r^2 = dx^2 + dy^2, so per strip the lane keeps the column phases (or dx, or
