@@ -37,8 +37,12 @@ def compare(gg, ref, variant, tag):
 
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("shape", [(64, 48, 37), (100, 75, 130), (16, 16, 64), (33, 1, 5),
-                                   (1, 40, 3)])
+                                   (1, 40, 3), (96, 5, 64), (160, 3, 200)])
 def test_small_full(oracle_mod, variant, shape):
+    """Full-grid gradients against the oracle.  (96, 5, 64) and (160, 3, 200)
+    give runs of 7-8 strip-rows over strips of 5 or 3 rows, so the priority
+    quarters of a run fall at odd row offsets inside and across strip
+    segments."""
     nx, ny, n = shape
     dev = device()
     c = W.random_cloud(200 + n, n, nx, ny, zlo=0.2, zhi=1.0, alo=-1.0, ahi=1.0, margin=30)
