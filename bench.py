@@ -66,11 +66,13 @@ SLOTS = {k: FP32_OPS[k] + TRANS_SLOTS * TRANS_OPS[k] for k in FP32_OPS}
 # The practical ceiling: each kernel's per-interaction instruction mix run
 # alone by the probe (issue-bound, 8 resident waves per SIMD, operands where
 # the kernel holds them), in CU clocks per 64 interactions.  The recurrence
+# forward issues Gamma += delta, the cosine and an FMA with A from an SGPR,
+# plus one add per 4 interactions (delta += Delta, shared by 4 rows).  The recurrence
 # adjoint issues an add of two VGPRs, sine, cosine and three FMAs with G from
 # an SGPR; the compensated adjoint two products, two FMAs (sin and cos by the
 # addition theorem) and the same three FMAs.
-MIX_CLOCKS = {"fwd_plain": 6.116, "fwd_compensated": 3.685, "adj_plain": 9.331,
-              "adj_compensated": 4.033, "adj_recurrence": 7.839}
+MIX_CLOCKS = {"fwd_plain": 6.116, "fwd_compensated": 3.685, "fwd_recurrence": 3.966,
+              "adj_plain": 9.331, "adj_compensated": 4.033, "adj_recurrence": 7.839}
 CU_CLOCKS_PER_S = 256 * 2.4e9
 # The separable variant is a different algorithm, bound by the FP32 matrix
 # cores (dense MFMA FP32 peak 157.3 TFLOP/s): the forward is one GEMM of

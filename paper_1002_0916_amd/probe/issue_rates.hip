@@ -35,7 +35,7 @@
   } while (0)
 
 constexpr int kChains = 8;
-constexpr int kModes = 21;
+constexpr int kModes = 22;
 const char* const kNames[kModes] = {
     "fma (v, s, s)",  "fma (v, v, v)",   "add (v, s)",        "add (v, v)",
     "fract",          "cos",             "sin",               "cos + sin",
@@ -50,7 +50,8 @@ const char* const kNames[kModes] = {
     "adj factored sums: 4 fma (G in SGPR)",
     "adj factored sums: 4 fma (G in VGPR)",
     "fwd addition: mul, fma, fma (cY, sY, A in VGPRs)",
-    "fwd addition: mul, fma, fma (cY, sY, A in SGPRs)"};
+    "fwd addition: mul, fma, fma (cY, sY, A in SGPRs)",
+    "fwd recurrence: add, cos, fma (A in SGPR) + 1/4 add"};
 
 // Eight distinct wave-uniform values (SGPRs, from the kernel arguments).
 struct Uniform {
@@ -98,8 +99,8 @@ __global__ void rate(float* out, int iters, float a, float b, Uniform u,
   // products stay in the loop.
   float bw = bv, cw = av;
   for (int it = 0; it < iters; ++it) {
-    if (MODE >= 16) bw = bw + a;
-    if (MODE >= 17) cw = cw + b;
+    if (MODE >= 16 && MODE <= 20) bw = bw + a;
+    if (MODE >= 17 && MODE <= 20) cw = cw + b;
 #pragma unroll
     for (int k = 0; k < kChains; ++k) {
       if (MODE == 0) x[k] = __builtin_fmaf(x[k], a, b);
@@ -166,6 +167,13 @@ __global__ void rate(float* out, int iters, float a, float b, Uniform u,
         const float cy = MODE == 19 ? cw : row[k], sy = MODE == 19 ? bw : row[8 + k];
         const float ct = __builtin_fmaf(x[k], cy, -(y[k] * sy));
         s0[k] = __builtin_fmaf(MODE == 19 ? av : a, ct, s0[k]);
+      }
+      if (MODE == 21) {  // Gamma += delta, cos, A * c + acc (A in an SGPR)
+        // chains k = 4c + i: column c of the lane's pair, row i; the rows of
+        // a column share delta, which steps by Delta once per column
+        s0[k] = __builtin_fmaf(a, __builtin_amdgcn_cosf(x[k]), s0[k]);
+        x[k] = x[k] + y[k & ~3];
+        if ((k & 3) == 3) y[k & ~3] = y[k & ~3] + bv;
       }
       if (MODE == 15) {  // fract(Prev (dx^2 + RY)), sin, cos, 3 sums
         const float tt = __builtin_amdgcn_fractf(bv * __builtin_fmaf(x[k], x[k], y[k]));
@@ -367,7 +375,8 @@ int main() {
   hipEvent_t e0, e1;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
-  typedef Table<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20> Modes;
+  typedef Table<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21>
+      Modes;
   const Launch* fns = Modes::fns;
   // One 64-lane instruction per CU per clock.
   const double per_cycle = (double)p.multiProcessorCount * 64 * (p.clockRate * 1e3);
