@@ -2,7 +2,8 @@
 (`bench.py --summarize`), on small synthetic CSV files: the copy calibration
 of FETCH_SIZE / WRITE_SIZE, the per-interaction counter arithmetic, the
 trace-versus-event table, and the rule that a kernel's recorded traffic is
-withheld once its sources change.  No GPU."""
+withheld once its sources change; that the committed record matches the
+headline kernels' current sources; and the one-GPU guard.  No GPU."""
 import csv
 import importlib.util
 import json
@@ -258,3 +259,24 @@ def test_library_gemm_summary_matches_kernels_by_format_and_fold(bench, tmp_path
     assert "| f32 | 60.0 | 134 | 85.3% | 80.0 | 101 | 64.0% | 0.75x |" in text
     # a format with no kernel in the stats run gets dashes
     assert "| bf16 | 20.0 | 403 | 16.1% | - | - | - | - |" in text
+
+
+def test_committed_traffic_matches_the_headline_kernels(bench):
+    """The committed counter record still describes the current sources of
+    the headline step's two kernels, so the bench line carries their traffic
+    (a code edit to either kernel withholds it until the counters are taken
+    again)."""
+    for kernel in ("adj_partial_kernel<1>", "fwd_comp_kernel"):
+        assert bench.measured_traffic(kernel) is not None, kernel
+        assert bench.measured_traffic(kernel, key="traffic_bytes_sized") is not None, kernel
+
+
+def test_more_than_one_gpu_is_refused():
+    """One GPU only: --gpus above 1 exits with a message and a non-zero
+    status before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU only" in r.stderr
