@@ -57,6 +57,35 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_variant(lib_path: str, defines, verbose: bool = False) -> str:
+    """Builds the library with extra preprocessor definitions into
+    ``lib_path`` (objects in their own build folder): diagnostic builds such
+    as the adjoint's wave trace (``CGH_WAVE_TRACE``).  Not used by the
+    package, which loads ``libcgh.so``."""
+    tag = os.path.splitext(os.path.basename(lib_path))[0]
+    bdir = os.path.join(BUILD, tag)
+    os.makedirs(bdir, exist_ok=True)
+    flags = [*HIPFLAGS, *("-D" + d for d in defines)]
+
+    def comp(src):
+        obj = os.path.join(bdir, os.path.basename(src) + ".o")
+        r = subprocess.run([HIPCC, *flags, "-c", src, "-o", obj], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr))
+        return obj
+
+    srcs = sources()
+    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(comp, srcs))
+    r = subprocess.run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", lib_path],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc link failed:\n%s" % r.stderr)
+    if verbose:
+        print("built", lib_path)
+    return lib_path
+
+
 PROBE_SRC = os.path.join(HERE, "probe", "issue_rates.hip")
 PROBE_BIN = os.path.join(HERE, "probe", "issue_rates")
 

@@ -46,6 +46,16 @@
 
 namespace cgh {
 
+#ifdef CGH_WAVE_TRACE
+// Wave trace of a diagnostic build (compiled only with -DCGH_WAVE_TRACE, never
+// into the library that build() makes): per wave of the last adjoint launch,
+// indexed by its linear workgroup id, the 100 MHz constant clock at its start
+// and end, its hardware ids (HW_ID in the low word, XCC_ID in the high word)
+// and the shader-clock cycles between start and end.
+constexpr unsigned kWaveTraceMax = 65536;
+__device__ ulonglong4 g_wave_trace[kWaveTraceMax];
+#endif
+
 namespace {
 
 // KIND: kAdjPlain, kAdjCompensated (the rows' cY, sY from the row table,
@@ -64,6 +74,10 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     int npad, const float2* __restrict__ rtab, const float* __restrict__ ctab,
     float4* __restrict__ partial) {
   constexpr bool kComp = KIND == kAdjCompensated || KIND == kAdjCompensatedInline;
+#ifdef CGH_WAVE_TRACE
+  const unsigned long long trace_t0 = __builtin_amdgcn_s_memrealtime();
+  const unsigned long long trace_c0 = __builtin_amdgcn_s_memtime();
+#endif
   // Neighbouring runs and all point groups of a run share G and the tables:
   // keep them on one XCD.
   const unsigned tile = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
@@ -271,6 +285,17 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
     q += row1 - row0;
   }
   partial[(int64_t)run * npad + j] = make_float4(Sc0 + Sc1, Sx, Sy, Sr);
+#ifdef CGH_WAVE_TRACE
+  const unsigned long long trace_c1 = __builtin_amdgcn_s_memtime();
+  const unsigned long long trace_t1 = __builtin_amdgcn_s_memrealtime();
+  const unsigned hw_id = __builtin_amdgcn_s_getreg((31 << 11) | 4);   // HW_ID
+  const unsigned xcc_id = __builtin_amdgcn_s_getreg((31 << 11) | 20);  // XCC_ID
+  const unsigned wl = blockIdx.y * gridDim.x + blockIdx.x;
+  if (threadIdx.x == 0 && wl < kWaveTraceMax)
+    g_wave_trace[wl] = make_ulonglong4(trace_t0, trace_t1,
+                                       ((unsigned long long)xcc_id << 32) | hw_id,
+                                       trace_c1 - trace_c0);
+#endif
 }
 
 __global__ __launch_bounds__(kAdjFinPoints* kAdjFinSlices) void adj_finalize_kernel(
@@ -343,6 +368,14 @@ __global__ __launch_bounds__(256) void pad_g_kernel(const float* __restrict__ g,
 }
 
 }  // namespace
+
+#ifdef CGH_WAVE_TRACE
+extern "C" int cgh_wave_trace_read(void* host, size_t bytes) {
+  if (!host || bytes > sizeof(g_wave_trace)) return 1;
+  return hipMemcpyFromSymbol(host, HIP_SYMBOL(g_wave_trace), bytes, 0,
+                             hipMemcpyDeviceToHost) == hipSuccess ? 0 : 1;
+}
+#endif
 
 hipError_t launch_pad_g(const Plan& p, const float* g, float* gpad, hipStream_t s) {
   const int ldp = p.nsx * kAdjCols;
