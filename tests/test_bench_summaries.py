@@ -280,3 +280,18 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "one GPU only" in r.stderr
+
+
+def test_ramp_summary_against_the_steady_state(bench, tmp_path):
+    run = tmp_path / "run"
+    run.mkdir()
+    blocks = [{"first_step": 20 * i, "fwd_ms": 0.2 if i >= 3 else 0.25,
+               "adj_ms": 0.3 if i >= 3 else 0.36} for i in range(20)]
+    line = {"mode": "ramp", "variant": "compensated", "steps": 400, "block": 20,
+            "blocks": blocks}
+    (run / "ramp.log").write_text(json.dumps(line) + "\n")
+    bench.summarize("ramp", str(run))
+    text = open(os.path.join(bench.PROFILES, "clock_ramp_paper_1920x1024.md")).read()
+    # the steady state is the mean of the second half of the blocks
+    assert "| 0-19 | 0.2500 | 1.250 | 0.3600 | 1.200 |" in text
+    assert "| 380-399 | 0.2000 | 1.000 | 0.3000 | 1.000 |" in text
