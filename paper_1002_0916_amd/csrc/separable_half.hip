@@ -61,11 +61,21 @@ __global__ __launch_bounds__(256) void absmax_kernel(const float* __restrict__ v
   if (((uintptr_t)v & 15u) == 0) {
     const int64_t n4 = count / 4;
     const float4* v4 = reinterpret_cast<const float4*>(v);
-    for (int64_t i = first; i < n4; i += stride) {
-      const float4 q = v4[i];
+    auto take = [&](const float4& q) {
       m = max(m, max(max(__float_as_uint(fabsf(q.x)), __float_as_uint(fabsf(q.y))),
                      max(__float_as_uint(fabsf(q.z)), __float_as_uint(fabsf(q.w)))));
+    };
+    // Eight loads in flight per thread before their maxima are taken: the
+    // pass is bound by memory latency, not by the max operations.
+    int64_t i = first;
+    for (; i + 7 * stride < n4; i += 8 * stride) {
+      float4 q[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) q[k] = v4[i + k * stride];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) take(q[k]);
     }
+    for (; i < n4; i += stride) take(v4[i]);
     for (int64_t i = 4 * n4 + first; i < count; i += stride)
       m = max(m, __float_as_uint(fabsf(v[i])));
   } else {
