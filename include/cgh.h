@@ -144,6 +144,26 @@ int cgh_forward(const float* x, const float* y, const float* z, const float* a, 
                 float* hologram, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Forward with the residual of a target, for a loss L = 0.5 ||I - T||^2 whose
+ * upstream gradient dL/dI = I - T feeds cgh_backward (the chain rule on
+ * Eq. (1), Section 1).  Writes I exactly as cgh_forward (the same bits) and
+ *   residual[h] = hologram[h] - target[h]   (one FP32 subtraction each),
+ * in the compensated forward's own store pass, after the other forwards as
+ * one more kernel on the same stream.
+ *   target       device float32[ny][nx], read only.
+ *   hologram     device float32[ny][nx], overwritten with I.
+ *   residual     device float32[ny][nx], overwritten with I - T.
+ * The three arrays must not overlap (the same pointer twice returns
+ * CGH_EINVAL; partial overlaps are not detected).  Workspace as cgh_forward
+ * (cgh_workspace_bytes with CGH_OP_FORWARD).  n = 0 writes I = 0 and
+ * residual = -target.  Other errors as cgh_forward.
+ */
+int cgh_forward_residual(const float* x, const float* y, const float* z, const float* a,
+                         int64_t n, int32_t nx, int32_t ny, double pitch, double wavelength,
+                         int32_t variant, const float* target, float* hologram, float* residual,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Forward, Eq. (1), with FP64 phase arithmetic and FP64 output: the
  * on-device reference used to measure the FP32 variants at full size.
  *   hologram     device float64[ny][nx], overwritten.

@@ -48,7 +48,7 @@ VARIANTS = {"plain": PLAIN, "fast": PLAIN, "compensated": COMPENSATED, "comp": C
 
 EXPORTED = ("cgh_workspace_bytes", "cgh_forward", "cgh_forward_f64", "cgh_backward",
             "cgh_strerror", "cgh_version", "cgh_profile_enable", "cgh_profile_read",
-            "cgh_profile_read_each", "cgh_forward_noalloc")
+            "cgh_profile_read_each", "cgh_forward_noalloc", "cgh_forward_residual")
 
 _lib = None
 _lock = threading.Lock()
@@ -79,6 +79,9 @@ def load_library():
         lib.cgh_forward_noalloc.argtypes = [vp, vp, vp, vp, i64, i32, i32, f64, f64, i32, vp,
                                             vp]
         lib.cgh_forward_noalloc.restype = ctypes.c_int
+        lib.cgh_forward_residual.argtypes = [vp, vp, vp, vp, i64, i32, i32, f64, f64, i32, vp,
+                                             vp, vp, vp, ctypes.c_size_t, vp]
+        lib.cgh_forward_residual.restype = ctypes.c_int
         lib.cgh_forward_f64.argtypes = [vp, vp, vp, vp, i64, i32, i32, f64, f64, vp, vp,
                                         ctypes.c_size_t, vp]
         lib.cgh_forward_f64.restype = ctypes.c_int
@@ -184,6 +187,40 @@ def forward(x, y, z, a, nx: int, ny: int, pitch: float = 8e-6, wavelength: float
                            float(pitch), float(wavelength), v, out.data_ptr(), ws, wsb,
                            stream.cuda_stream))
     return out
+
+
+def forward_residual(x, y, z, a, target: torch.Tensor, nx: int, ny: int, pitch: float = 8e-6,
+                     wavelength: float = 633e-9, variant="compensated",
+                     out: torch.Tensor | None = None,
+                     residual: torch.Tensor | None = None) -> tuple[torch.Tensor, torch.Tensor]:
+    """(I, I - target) through ``cgh_forward_residual``: I as ``forward``, and
+    the residual (the upstream gradient of 0.5 ||I - T||^2) in the same call."""
+    lib = load_library()
+    n, dev = _points(x, y, z, a)
+    nx, ny = _sizes(nx, ny)
+    v = variant_id(variant)
+
+    def grid(t, name):
+        if t is None:
+            return torch.empty((ny, nx), dtype=torch.float32, device=dev)
+        if (t.dtype != torch.float32 or t.device != dev or not t.is_contiguous()
+                or t.numel() != nx * ny):
+            raise ValueError("%s must be a contiguous float32 tensor of ny*nx on x's device"
+                             % name)
+        return t
+
+    if target is None:
+        raise ValueError("target is required")
+    target = grid(target, "target")
+    out = grid(out, "out")
+    residual = grid(residual, "residual")
+    stream = torch.cuda.current_stream(dev)
+    ws, wsb = _workspace(dev, stream, workspace_bytes(n, nx, ny, v, OP_FORWARD))
+    _check(lib.cgh_forward_residual(x.data_ptr(), y.data_ptr(), z.data_ptr(), a.data_ptr(), n,
+                                    nx, ny, float(pitch), float(wavelength), v,
+                                    target.data_ptr(), out.data_ptr(), residual.data_ptr(), ws,
+                                    wsb, stream.cuda_stream))
+    return out, residual
 
 
 def forward_noalloc(x, y, z, a, nx: int, ny: int, pitch: float = 8e-6,

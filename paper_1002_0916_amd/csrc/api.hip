@@ -312,8 +312,12 @@ EventPair profile_begin(int kernel, hipStream_t s, bool timed = true) {
     e = P.pool.back();
     P.pool.pop_back();
   } else {
-    if (hipEventCreate(&e.start) != hipSuccess) return EventPair{nullptr, nullptr};
-    if (hipEventCreate(&e.stop) != hipSuccess) {
+    // Timing-only events: no system-scope fence at record, so recording them
+    // neither writes back nor invalidates the caches between the kernels they
+    // bracket (their times are read after the stream has synchronised).
+    if (hipEventCreateWithFlags(&e.start, hipEventDisableSystemFence) != hipSuccess)
+      return EventPair{nullptr, nullptr};
+    if (hipEventCreateWithFlags(&e.stop, hipEventDisableSystemFence) != hipSuccess) {
       (void)hipEventDestroy(e.start);
       return EventPair{nullptr, nullptr};
     }
@@ -499,10 +503,13 @@ int scratch_address(void** out) {
 // Enqueues the forward for plan p with its scratch at `workspace` (the
 // caller's workspace, or the static scratch), after the argument checks.
 // timed = false skips the event timing (which creates events), for the
-// allocation-free entry point.
+// allocation-free entry point.  With target and residual it also writes
+// residual = hologram - target: fused into the compensated forward's store,
+// a separate elementwise launch after the other forwards.
 int forward_run(const Plan& p, void* workspace, const float* x, const float* y, const float* z,
                 const float* a, double pitch, double wavelength, float* hologram,
-                hipStream_t s, bool timed = true);
+                hipStream_t s, bool timed = true, const float* target = nullptr,
+                float* residual = nullptr);
 
 }  // namespace cgh
 
@@ -533,6 +540,29 @@ int cgh_forward(const float* x, const float* y, const float* z, const float* a, 
   return forward_run(p, workspace, x, y, z, a, pitch, wavelength, hologram, s, true);
 }
 
+int cgh_forward_residual(const float* x, const float* y, const float* z, const float* a,
+                         int64_t n, int32_t nx, int32_t ny, double pitch, double wavelength,
+                         int32_t variant, const float* target, float* hologram, float* residual,
+                         void* workspace, size_t workspace_bytes, void* stream) {
+  int rc = check_common(x, y, z, a, n, nx, ny, pitch, wavelength);
+  if (rc) return rc;
+  if (!valid_variant(variant)) return CGH_EINVAL;
+  if (!hologram || !target || !residual) return CGH_EINVAL;
+  if (residual == hologram || residual == target || hologram == target) return CGH_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t count = (int64_t)nx * ny;
+  if (n == 0) {
+    hipError_t e = launch_fill_zero_f32(hologram, count, s);
+    if (e == hipSuccess) e = launch_residual(hologram, target, residual, count, s);
+    return hip_status(e);
+  }
+  const Plan p = make_plan(n, nx, ny, variant, CGH_OP_FORWARD);
+  rc = check_workspace(p, workspace, workspace_bytes);
+  if (rc) return rc;
+  return forward_run(p, workspace, x, y, z, a, pitch, wavelength, hologram, s, true, target,
+                     residual);
+}
+
 int cgh_forward_noalloc(const float* x, const float* y, const float* z, const float* a,
                         int64_t n, int32_t nx, int32_t ny, double pitch, double wavelength,
                         int32_t variant, float* hologram, void* stream) {
@@ -560,7 +590,7 @@ namespace cgh {
 
 int forward_run(const Plan& p, void* workspace, const float* x, const float* y, const float* z,
                 const float* a, double pitch, double wavelength, float* hologram,
-                hipStream_t s, bool timed) {
+                hipStream_t s, bool timed, const float* target, float* residual) {
   const int32_t variant = p.variant;
   const int64_t n = p.n;
   const Workspace w = carve(p, workspace);
@@ -569,12 +599,19 @@ int forward_run(const Plan& p, void* workspace, const float* x, const float* y, 
                      ? launch_prep_ytab(x, y, z, a, pitch, wavelength, p, w, s)
                      : launch_prep(x, y, z, a, n, p.npad, pitch, wavelength, w, false, s);
   if (e != hipSuccess) return CGH_EHIP;
-  if (variant == CGH_SEPARABLE) return forward_separable(p, w, hologram, s, timed);
-  if (half_mode(variant) >= 0) return forward_separable_half(p, w, hologram, s, timed);
+  auto separate_residual = [&](int rc) {
+    if (rc != CGH_OK || !residual) return rc;
+    return hip_status(launch_residual(hologram, target, residual, (int64_t)p.nx * p.ny, s));
+  };
+  if (variant == CGH_SEPARABLE)
+    return separate_residual(forward_separable(p, w, hologram, s, timed));
+  if (half_mode(variant) >= 0)
+    return separate_residual(forward_separable_half(p, w, hologram, s, timed));
   if (variant == CGH_COMPENSATED) {
     const EventPair ev = profile_begin(CGH_KERNEL_FWD_COMPENSATED, s, timed);
-    e = launch_fwd_comp(p, w, hologram, s);
+    e = launch_fwd_comp(p, w, hologram, s, target, residual);
     profile_end(CGH_KERNEL_FWD_COMPENSATED, ev, s);
+    return hip_status(e);
   } else if (variant == CGH_RECURRENCE) {
     const EventPair ev = profile_begin(CGH_KERNEL_FWD_RECURRENCE, s, timed);
     e = launch_fwd_rec(p, w, hologram, s);
@@ -584,7 +621,7 @@ int forward_run(const Plan& p, void* workspace, const float* x, const float* y, 
     e = launch_fwd_plain(p, w, hologram, s);
     profile_end(CGH_KERNEL_FWD_PLAIN, ev, s);
   }
-  return hip_status(e);
+  return separate_residual(hip_status(e));
 }
 
 }  // namespace cgh

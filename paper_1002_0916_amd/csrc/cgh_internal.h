@@ -251,7 +251,13 @@ hipError_t launch_prep_rtab(const float* x, const float* y, const float* z, cons
                             double pitch, double wavelength, const Plan& p, const Workspace& w,
                             hipStream_t s);
 hipError_t launch_fwd_plain(const Plan& p, const Workspace& w, float* out, hipStream_t s);
-hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s);
+// With target and residual (both or neither) the compensated forward also
+// writes residual = out - target in its store.
+hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s,
+                           const float* target = nullptr, float* residual = nullptr);
+// residual = hologram - target over count elements (the other forwards).
+hipError_t launch_residual(const float* hologram, const float* target, float* residual,
+                           int64_t count, hipStream_t s);
 hipError_t launch_fwd_rec(const Plan& p, const Workspace& w, float* out, hipStream_t s);
 hipError_t launch_fwd_f64(const Plan& p, const Workspace& w, double* out, hipStream_t s);
 hipError_t launch_pad_g(const Plan& p, const float* g, float* gpad, hipStream_t s);

@@ -201,7 +201,9 @@ __device__ __forceinline__ void fwd_comp_body(const float* __restrict__ xrec,
                                                   const float* __restrict__ xtab,
                                                   const float* __restrict__ amp,
                                                   const float* __restrict__ ytab, int npad,
-                                                  int nx, int ny, float* __restrict__ out) {
+                                                  int nx, int ny, float* __restrict__ out,
+                                                  const float* __restrict__ tgt,
+                                                  float* __restrict__ res) {
   static_assert(kCompRows == 4, "a wave's row phases of one point are one float4");
   __shared__ float xs[kTile * kTilePitch];
   __shared__ float4 ys[kCompWaves][kTile];
@@ -288,24 +290,41 @@ __device__ __forceinline__ void fwd_comp_body(const float* __restrict__ xrec,
       }
     }
   }
+  // The hologram, and with a target T the residual I - T (the upstream
+  // gradient of 0.5 ||I - T||^2) in the same pass.
   const int y0 = grp * kCompRows;
   if (col < nx) {
 #pragma unroll
-    for (int i = 0; i < kCompRows; ++i)
-      if (y0 + i < ny) out[(int64_t)(y0 + i) * nx + col] = acc[i];
+    for (int i = 0; i < kCompRows; ++i) {
+      if (y0 + i >= ny) continue;
+      const int64_t idx = (int64_t)(y0 + i) * nx + col;
+      out[idx] = acc[i];
+      if (res) res[idx] = acc[i] - tgt[idx];
+    }
   }
 }
 
 __global__ __launch_bounds__(kCompThreads) void fwd_comp_kernel(
     const float* __restrict__ xtab, const float* __restrict__ amp, const float* __restrict__ ytab,
-    int npad, int nx, int ny, float* __restrict__ out) {
-  fwd_comp_body<true>(nullptr, xtab, amp, ytab, npad, nx, ny, out);
+    int npad, int nx, int ny, float* __restrict__ out, const float* __restrict__ tgt,
+    float* __restrict__ res) {
+  fwd_comp_body<true>(nullptr, xtab, amp, ytab, npad, nx, ny, out, tgt, res);
 }
 
 __global__ __launch_bounds__(kCompThreads) void fwd_comp_inline_kernel(
     const float* __restrict__ xrec, const float* __restrict__ amp, const float* __restrict__ ytab,
-    int npad, int nx, int ny, float* __restrict__ out) {
-  fwd_comp_body<false>(xrec, nullptr, amp, ytab, npad, nx, ny, out);
+    int npad, int nx, int ny, float* __restrict__ out, const float* __restrict__ tgt,
+    float* __restrict__ res) {
+  fwd_comp_body<false>(xrec, nullptr, amp, ytab, npad, nx, ny, out, tgt, res);
+}
+
+// The residual G = I - T of a finished hologram, for the forwards without a
+// fused one.
+__global__ __launch_bounds__(256) void residual_kernel(const float* __restrict__ I,
+                                                       const float* __restrict__ T,
+                                                       float* __restrict__ G, int64_t count) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) G[t] = I[t] - T[t];
 }
 
 // FP64 reference: rho = Prev ((x_h - x_j)^2 + (y_h - y_j)^2) in revolutions,
@@ -367,15 +386,25 @@ hipError_t launch_fwd_rec(const Plan& p, const Workspace& w, float* out, hipStre
   }
 }
 
-hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s) {
+hipError_t launch_fwd_comp(const Plan& p, const Workspace& w, float* out, hipStream_t s,
+                           const float* target, float* residual) {
   if (w.xtab)
     hipLaunchKernelGGL(fwd_comp_kernel, dim3(p.fwd_gx, p.comp_gy), dim3(kCompThreads), 0, s,
                        (const float*)w.xtab, (const float*)w.amp, (const float*)w.ytab,
-                       (int)p.npad, p.nx, p.ny, out);
+                       (int)p.npad, p.nx, p.ny, out, target, residual);
   else
     hipLaunchKernelGGL(fwd_comp_inline_kernel, dim3(p.fwd_gx, p.comp_gy), dim3(kCompThreads), 0,
                        s, (const float*)w.xrec, (const float*)w.amp, (const float*)w.ytab,
-                       (int)p.npad, p.nx, p.ny, out);
+                       (int)p.npad, p.nx, p.ny, out, target, residual);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const float* hologram, const float* target, float* residual,
+                           int64_t count, hipStream_t s) {
+  const unsigned blocks = grid_blocks(count, 256);
+  if (!blocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(residual_kernel, dim3(blocks), dim3(256), 0, s, hologram, target, residual,
+                     count);
   return hipGetLastError();
 }
 

@@ -179,6 +179,31 @@ def test_forward_rejects_bad_arguments(lib, case):
                                  args["nx"], args["ny"], args["pitch"], args["wl"], args["v"],
                                  args["out"], None)
     assert rc == B.CGH_EINVAL
+    # and so does the forward with a residual (target and residual elsewhere)
+    rc = lib.cgh_forward_residual(args["x"], args["y"], args["z"], args["a"], args["n"],
+                                  args["nx"], args["ny"], args["pitch"], args["wl"], args["v"],
+                                  ctypes.c_void_p(512), args["out"], ctypes.c_void_p(768), p,
+                                  1 << 30, None)
+    assert rc == B.CGH_EINVAL
+
+
+def test_forward_residual_rejects_missing_or_aliased_grids(lib):
+    """cgh_forward_residual needs three distinct grids (target, hologram,
+    residual) and the forward's workspace; all checked on the host."""
+    from paper_1002_0916_amd import binding as B
+
+    p = ctypes.c_void_p(256)
+    t, h, r = ctypes.c_void_p(4096), ctypes.c_void_p(8192), ctypes.c_void_p(12288)
+
+    def call(target, holo, res, ws=p, wsb=1 << 30):
+        return lib.cgh_forward_residual(p, p, p, p, 100, 64, 64, 8e-6, 633e-9, B.COMPENSATED,
+                                        target, holo, res, ws, wsb, None)
+
+    for args in ((None, h, r), (t, None, r), (t, h, None), (t, h, h), (t, h, t), (t, t, r)):
+        assert call(*args) == B.CGH_EINVAL, args
+    need = lib.cgh_workspace_bytes(100, 64, 64, B.COMPENSATED, B.OP_FORWARD)
+    assert call(t, h, r, p, need - 1) == B.CGH_EWORKSPACE
+    assert call(t, h, r, None, need) == B.CGH_EWORKSPACE
 
 
 def test_noalloc_rejects_problems_beyond_its_scratch(lib):
