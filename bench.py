@@ -936,7 +936,8 @@ def summarize_stats(root):
              "The run times every variant of the step (50 timed + 5 warm-up steps each, one "
              "graph capture and 50 replays per variant, the accuracy checks and the CPU "
              "baseline).  Kernel "
-             "names: fwd_comp_kernel / adj_partial_kernel<1> (compensated), fwd_plain_kernel / "
+             "names: fwd_comp_residual_kernel (the step's forward, which also writes G = I - T) "
+             "/ adj_partial_kernel<1> (compensated), fwd_plain_kernel / "
              "adj_partial_kernel<0> (plain), fwd_rec_kernel<K, R> / adj_partial_kernel<2> "
              "(recurrence), gemm_f32_kernel (separable FP32), gemm_half_kernel<format, fold> "
              "(format 2 = fp16 hi/lo, 0 = fp16, 1 = bf16; fold 0 = forward, 1 and 2 = the "
@@ -966,7 +967,7 @@ def summarize_stats(root):
             line = json_line(f) or line
     if line is not None:
         traced = {_kernel_short(r["Name"]): float(r["AverageNs"]) / 1e3 for r in rows}
-        pairs = [("fwd_comp_kernel", "compensated", "fwd"),
+        pairs = [("fwd_comp_residual_kernel", "compensated", "fwd"),
                  ("adj_partial_kernel<1>", "compensated", "adj"),
                  ("fwd_plain_kernel", "plain", "fwd"), ("adj_partial_kernel<0>", "plain", "adj"),
                  ("fwd_rec_kernel<8, 4, 2>", "recurrence", "fwd"),
@@ -1008,9 +1009,9 @@ TRAFFIC_KERNELS = {
                               "4 waves per SIMD)"),
     "adj_partial_kernel<2>": (["adjoint.hip", "phase.h", "records.h", "cgh_internal.h"],
                               "G 7.86 MB + inputs 0.02 MB + run partials 9.44 MB (576 runs)"),
-    "fwd_comp_kernel": (["forward.hip", "phase.h", "cgh_internal.h"],
-                        "row table 4.19 MB + column table 7.86 MB + amplitudes + "
-                        "hologram 7.86 MB + target 7.86 MB + residual 7.86 MB = 35.6 MB"),
+    "fwd_comp_residual_kernel": (["forward.hip", "phase.h", "cgh_internal.h"],
+                                 "row table 4.19 MB + column table 7.86 MB + amplitudes + "
+                                 "hologram 7.86 MB + target 7.86 MB + residual 7.86 MB = 35.6 MB"),
     "fwd_plain_kernel": (["forward.hip", "phase.h", "cgh_internal.h"],
                          "records 0.02 MB + hologram 7.86 MB"),
     "fwd_rec_kernel<8, 4, 2>": (["forward.hip", "phase.h", "cgh_internal.h"],
@@ -1218,7 +1219,8 @@ COUNTER_PASSES = (
 # Direct kernels per variant, with the roofline key of their algorithmic work
 # per interaction (FP32_OPS + TRANS_OPS instructions).
 COUNTER_KERNELS = {
-    "compensated": {"fwd_comp_kernel": "fwd_compensated", "adj_partial_kernel<1>": "adj_compensated"},
+    "compensated": {"fwd_comp_residual_kernel": "fwd_compensated",
+                    "adj_partial_kernel<1>": "adj_compensated"},
     "plain": {"fwd_plain_kernel": "fwd_plain", "adj_partial_kernel<0>": "adj_plain"},
     "recurrence": {"fwd_rec_kernel<8, 4, 2>": "fwd_recurrence",
                    "adj_partial_kernel<2>": "adj_recurrence"},

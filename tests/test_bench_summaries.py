@@ -131,7 +131,7 @@ def test_counter_summary_per_interaction(bench, tmp_path):
         text = f.read()
     # 4 VALU (1 transcendental) per interaction against the algorithmic 3 (1):
     # 2 FP32 ops + 4 slots for the cosine = 6 slots; VALU busy 50%
-    assert "| `fwd_comp_kernel` | 4.00 | 1.00 | 3 (1) | 6 | 50% | 0.250 | 0.0250 | 0.0000 |" in text
+    assert "| `fwd_comp_residual_kernel` | 4.00 | 1.00 | 3 (1) | 6 | 50% | 0.250 | 0.0250 | 0.0000 |" in text
     assert "| `adj_partial_kernel<2>` | 4.00 | 1.00 | 6 (2) | 12 | 50% |" in text
     assert "| 100 | 32.0 |" in text  # MFMA per dispatch, busy cycles per MFMA
 
@@ -266,7 +266,7 @@ def test_committed_traffic_matches_the_headline_kernels(bench):
     the headline step's two kernels, so the bench line carries their traffic
     (a code edit to either kernel withholds it until the counters are taken
     again)."""
-    for kernel in ("adj_partial_kernel<1>", "fwd_comp_kernel"):
+    for kernel in ("adj_partial_kernel<1>", "fwd_comp_residual_kernel"):
         assert bench.measured_traffic(kernel) is not None, kernel
         assert bench.measured_traffic(kernel, key="traffic_bytes_sized") is not None, kernel
 
