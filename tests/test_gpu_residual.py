@@ -62,3 +62,22 @@ def test_residual_of_no_points():
     torch.cuda.synchronize()
     assert torch.count_nonzero(I).item() == 0
     assert torch.equal(G, -T)
+
+
+def test_residual_without_the_column_table():
+    """4096 columns and 16448 points: the forward's column table would take
+    4096 x 16448 x 4 B = 269.5 MB, above its 256 MiB bound, so the forward
+    forms the x-phases itself (the inline kernels).  The residual instance of
+    that kernel writes the same I as the one without a target."""
+    nx, ny, n = 4096, 4, 16448
+    assert nx * n * 4 > 256 << 20
+    dev = device()
+    say("residual, inline x-phases", (nx, ny, n))
+    c = W.random_cloud(907, n, nx, ny, zlo=0.2, zhi=1.0, alo=-1.0, ahi=1.0, margin=30)
+    x, y, z, a = to_dev(c, dev)
+    T = _target(nx, ny, 908, dev)
+    I, G = B.forward_residual(x, y, z, a, T, nx, ny, variant="compensated")
+    ref = B.forward(x, y, z, a, nx, ny, variant="compensated")
+    torch.cuda.synchronize()
+    assert torch.equal(I, ref)
+    assert torch.equal(G, ref - T)
