@@ -84,8 +84,32 @@ __global__ __launch_bounds__(kAdjThreads) void adj_partial_kernel(
   const int run = (int)(tile / gridDim.y);
   const int j = (int)(tile % gridDim.y) * kWave + threadIdx.x;
   const int runs = (int)gridDim.x;
-  const int64_t q0 = strip_rows * run / runs;
-  const int64_t q1 = strip_rows * (run + 1) / runs;
+  // Run lengths.  xcd_tile hands each XCD a block of consecutive runs, whose
+  // workgroups it dispatches in run order.  When every block holds a whole
+  // number of runs per round of resident waves (runs a multiple of
+  // kAdjRounds * kXcds), the last 1/kAdjRounds of a block's runs are the
+  // last round; those runs are made 2/5 as long as the others (weights 2
+  // and 5, the block's total unchanged), and the dispatcher gives the short
+  // waves to the slots that free first, which evens out when the SIMDs
+  // finish.  Otherwise (few runs of many point groups) a round ends inside a
+  // run, and all runs keep one length.  Every run is a range of the
+  // strip-row order, [pos(run), pos(run + 1)), and the sums are reduced in
+  // run order.
+  const int64_t w_short = runs % (kAdjRounds * kXcds) == 0 ? 2 : 5;
+  auto weight_before = [&](int r) -> int64_t {
+    int64_t acc = 0;
+#pragma unroll
+    for (int b = 0; b < kXcds; ++b) {
+      const int lo = (int)((int64_t)runs * b / kXcds), hi = (int)((int64_t)runs * (b + 1) / kXcds);
+      const int t = hi - lo - (hi - lo) / kAdjRounds;  // runs before the last round
+      const int upto = min(max(r - lo, 0), hi - lo);
+      acc += 5 * (int64_t)min(upto, t) + w_short * (int64_t)max(upto - t, 0);
+    }
+    return acc;
+  };
+  const int64_t wsum = weight_before(runs);
+  const int64_t q0 = strip_rows * weight_before(run) / wsum;
+  const int64_t q1 = strip_rows * weight_before(run + 1) / wsum;
 
   // This lane's point (j >= n: a zero-amplitude padding point).
   const PointRecord rec = point_record(x, y, z, a, j, n, pitch, wavelength);
